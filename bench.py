@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of FRAM on one MI355X (gfx950).
+
+A step is one whole solve (Algorithm 1 with SDSN, discretisation and FP64
+objective) of the n = 4000 synthetic pair (Erdos-Renyi p = 0.3, U(0,1)
+weights, permuted copy with N(0, 0.05) edge noise and 10% outlier nodes,
+seed 2000), with A and B resident in HBM before timing starts
+(fram_solve_dev).  The headline value is solves/s of the mixed-precision path
+(BF16 MFMA GEMMs, FP32 SDSN, FP64 gamma/delta/objective); the same pair is
+also timed with FP32 GEMMs, and one extra profiled solve of each precision
+gives per-kernel device times from HIP events on the library's stream.
+
+Prints one JSON line.  Only one GPU is supported (--gpus 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import pathlib
+import sys
+import time
+
+ROOT = pathlib.Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+N_WORKLOAD = 4000
+THETA, ITERS, TOL, GAMMA_TOL = 2.0, 100, 1e-6, 1e-6
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pair, T, P):
+    """Time the FP64 oracle on a bounded sample of the same workload and scale
+    it to one solve: one gradient (two n x n GEMMs), 8 SDSN passes and one
+    exact LAP, scaled by the solve's outer iterations T and SDSN passes P."""
+    import numpy as np
+    from oracle import fram64 as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count()
+    As, Bs, _ = O.prescale(pair.A, pair.B)
+    n = pair.n
+    rng = np.random.default_rng(0)
+    N = rng.random((n, n)) ** 8
+    N /= N.sum(1, keepdims=True)
+    t0 = time.perf_counter()
+    X = As @ N @ Bs
+    t_grad = time.perf_counter() - t0
+    Y = (2.0 / 2) * X / X.max()
+    k = 8
+    t0 = time.perf_counter()
+    for _ in range(k):
+        Y = O.p2(O.p1(Y))
+    t_pass = (time.perf_counter() - t0) / k
+    t0 = time.perf_counter()
+    O.discretize(N)
+    t_lap = time.perf_counter() - t0
+    t_solve = T * t_grad + P * t_pass + t_lap
+    return {
+        "value": 1.0 / t_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"FP64 oracle at n={n}: 1 gradient ({t_grad:.2f}s), {k} SDSN passes "
+                   f"({t_pass:.3f}s each), 1 exact LAP ({t_lap:.2f}s); scaled to one solve "
+                   f"of T={T} outer iterations and P={P} SDSN passes -> {t_solve:.1f}s/solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the FRAM hot path here is a single-GPU build "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2508_00887_amd import Context
+
+    log("generating the n=4000 pair (seed 2000)")
+    pair = next(synth.config_pairs(2, [0]))
+    n = pair.n
+    dA = torch.from_numpy(pair.A).cuda()
+    dB = torch.from_numpy(pair.B).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = Context(0)
+
+    def solve(prec, profile=False):
+        return ctx.solve_dev(dA.data_ptr(), dB.data_ptr(), n, theta=THETA, iters=ITERS, tol=TOL,
+                             prec=prec, gamma_tol=GAMMA_TOL, stream=stream, profile=profile)
+
+    def timed(prec, steps, warmup):
+        for w in range(warmup):
+            solve(prec)
+            log(f"warmup {prec} {w + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for s in range(steps):
+            out = solve(prec)
+            log(f"step {prec} {s + 1}/{steps} done")
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, out
+
+    sec_mixed, (perm, obj, st) = timed(args.prec, args.steps, args.warmup)
+    acc = float(np.mean((perm == pair.perm)[pair.inlier]))
+    res = {}
+    if not args.no_fp32:
+        sec32, (perm32, obj32, st32) = timed("fp32", max(1, args.steps // 2), 1)
+        res["fp32"] = dict(solves_per_s=1.0 / sec32, ms_per_solve=1e3 * sec32,
+                           outer_iters=st32["outer_iters"], sdsn_passes=st32["sdsn_passes"],
+                           objective=obj32,
+                           accuracy=float(np.mean((perm32 == pair.perm)[pair.inlier])))
+    # Profiled solves: per-kernel device time (HIP events on the solve's stream).
+    prof = {}
+    for prec in [args.prec] + ([] if args.no_fp32 else ["fp32"]):
+        _, _, sp = solve(prec, profile=True)
+        log(f"profiled {prec} solve done")
+        flops = 4.0 * n ** 3 * sp["outer_iters"]
+        prof[prec] = dict(
+            gemm_tflops=flops / (sp["ms_gemm"] * 1e-3) / 1e12,
+            gemm_ms_per_launch=sp["ms_gemm"] / max(1, sp["gemm_launches"]),
+            sdsn_us_per_pass=1e3 * sp["ms_sdsn"] / max(1, sp["sdsn_launches"]),
+            sdsn_passes=sp["sdsn_launches"],
+            ms_gemm=sp["ms_gemm"], ms_sdsn=sp["ms_sdsn"], ms_stats=sp["ms_stats"],
+            ms_update=sp["ms_update"], outer_iters=sp["outer_iters"],
+        )
+    pm = prof[args.prec]
+    pass_bytes = 8.0 * n * n
+    achieved = pass_bytes / (pm["sdsn_us_per_pass"] * 1e-6) / 1e9
+    golden = ROOT / "tests" / "golden" / "fram_c2_seed2000.json"
+    rel_err = None
+    if golden.exists():
+        g = json.loads(golden.read_text())
+        rel_err = abs(obj - g["objective"]) / abs(g["objective"])
+    line = {
+        "metric": "solves/s + GEMM TFLOP/s mixed vs FP32 at n=4000, equal accuracy; serve p99 ms",
+        "value": 1.0 / sec_mixed,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec_mixed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "single pair n=4000, ER p=0.3, U(0,1) weights, noise 0.05, "
+                               "10% outliers, seed 2000",
+                   "n": n, "theta": THETA, "iters_cap": ITERS, "tol": TOL,
+                   "gamma_tol": GAMMA_TOL, "gemm_precision": args.prec},
+        "outer_iters": st["outer_iters"], "sdsn_passes": st["sdsn_passes"],
+        "accuracy": acc, "objective": obj, "rel_obj_err_vs_oracle": rel_err,
+        "host_lap": st["host_lap"],
+        "gemm_tflops": {k: v["gemm_tflops"] for k, v in prof.items()},
+        "profile": prof,
+        "roofline": {"bound": "hbm", "kernel": "sdsn_pass", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": pass_bytes},
+    }
+    if "fp32" in res:
+        line["fp32"] = res["fp32"]
+        line["speedup_vs_fp32"] = line["value"] / res["fp32"]["solves_per_s"]
+    if not args.no_cpu_baseline:
+        T = res["fp32"]["outer_iters"] if "fp32" in res else st["outer_iters"]
+        P = res["fp32"]["sdsn_passes"] if "fp32" in res else st["sdsn_passes"]
+        log("timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(pair, T, P)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

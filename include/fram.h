@@ -1,0 +1,215 @@
+/*
+ * fram.h -- C ABI of the MI355X (gfx950) FRAM library, libfram.so.
+ *
+ * FRAM (Frobenius-Regularized Assignment Matching) matches two graphs with
+ * nonnegative symmetric edge matrices A and B (Sec. 3, "Graph") by the
+ * projected fixed-point iteration of eq. (3):
+ *
+ *     X = A N B                      (gradient of eq. (1) without node term)
+ *     D = SDSN(X, theta)             (Algorithm 2: scaled doubly stochastic
+ *                                     normalisation, solves the FRA problem
+ *                                     of Theorem 1)
+ *     N = (1 - alpha) N + alpha D    (Algorithm 1, step 7)
+ *     delta = ||N_new - N_old||_F / ||N_new||_F   (App. B.2)
+ *
+ * and then discretises N to a permutation by the linear assignment of eq. (2)
+ * (Algorithm 1, step 10).  The GEMMs run on MFMA in FP32, BF16 or FP16 with
+ * FP32 accumulation; SDSN runs in FP32 with FP64 totals for gamma; delta and
+ * the final objective are accumulated in FP64.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are dense, row-major, n x n, leading dimension n unless an
+ *   explicit ld argument is given.
+ * - "theta" is the FRA strength of Theorem 1 (regulariser 1/theta); the
+ *   argument is named lambda where it plays that role at the boundary.  The
+ *   paper's node-term weight multiplies F F~^T, which this library does not
+ *   take (graphs without node attributes).
+ * - perm_out[i] = node of B matched to node i of A (M[i, perm_out[i]] = 1).
+ * - objective_out = sum_{k,l} A[k,l] * B[perm[k], perm[l]] = tr(A M B M^T),
+ *   i.e. 2 * Phi(M) of eq. (1) without node term, on the unscaled inputs,
+ *   accumulated in FP64.
+ * - Ownership: the caller owns every buffer it passes, host or device; the
+ *   library copies inputs in and writes outputs into caller storage and never
+ *   frees caller memory.  The library owns its device workspace, which lives
+ *   in the context and is released by fram_destroy.
+ * - Errors: return codes only.  Argument validation (NULL pointers, sizes,
+ *   non-finite/negative/asymmetric host inputs, theta <= 0, iters < 1,
+ *   tol < 0, HBM budget) happens before any device call.  Reaching an
+ *   iteration cap is not an error: the result is returned and the stats say
+ *   converged = 0 / sdsn_capped = 1.  A NaN/Inf in gamma or delta returns
+ *   FRAM_ENUMERIC; a HIP runtime failure returns FRAM_EDEVICE with the text in
+ *   fram_last_error().
+ * - Threading: one context per host thread.  A context is not re-entrant.
+ */
+#ifndef FRAM_H
+#define FRAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FRAM_OK = 0,
+  FRAM_EINVAL = 1,    /* invalid argument (checked before any device call)   */
+  FRAM_ENOMEM = 2,    /* problem exceeds the context's HBM budget            */
+  FRAM_EDEVICE = 3,   /* HIP runtime error; see fram_last_error()            */
+  FRAM_ENUMERIC = 4,  /* NaN/Inf met in gamma, delta or the objective        */
+  FRAM_EBUSY = 5      /* server queue full / slot unavailable                */
+} fram_status;
+
+/* Input type of the two GEMMs of Algorithm 1 step 5.  SDSN always runs in FP32
+ * and delta / objective in FP64 (the precision map of Algorithm 1, App. E,
+ * with TF32 replaced by FP16 or BF16, which gfx950 MFMA provides). */
+typedef enum { FRAM_FP32 = 0, FRAM_BF16 = 1, FRAM_FP16 = 2 } fram_precision;
+
+typedef struct {
+  int outer_iters;       /* outer iterations run (Algorithm 1 loop)                    */
+  int sdsn_passes;       /* SDSN passes summed over all outer iterations               */
+  int sdsn_passes_last;  /* passes of the last outer iteration                         */
+  int sdsn_passes_max;   /* largest pass count of any outer iteration                  */
+  int converged;         /* 1 if delta <= tol stopped the loop                         */
+  int sdsn_capped;       /* 1 if some SDSN call hit sdsn_max with gamma > gamma_tol    */
+  int host_lap;          /* 1 if the row argmax of N was not a permutation and the
+                            exact assignment was computed by the library's host solver */
+  int gemm_tile;         /* GEMM / SDSN tile edge used (64, 128 or 256)                 */
+  double delta;          /* last delta (App. B.2)                                      */
+  double gamma;          /* gamma of the last SDSN output (Sec. 5.2)                   */
+  double ms_total;       /* wall time of the call on the host, milliseconds            */
+  /* Filled only when fram_options.profile = 1 (HIP events around each launch,
+   * launches serialised): summed device milliseconds and launch counts. */
+  int gemm_launches;     /* GEMM launches (two per outer iteration)                    */
+  int sdsn_launches;     /* SDSN pass launches that did work                           */
+  double ms_gemm;        /* GEMM 1 + GEMM 2                                            */
+  double ms_sdsn;        /* SDSN passes (excluding the final gamma check)              */
+  double ms_stats;       /* tile statistics of X that start each SDSN call            */
+  double ms_update;      /* N update + delta                                           */
+} fram_stats;
+
+typedef struct {
+  fram_precision prec;   /* GEMM input type; default FRAM_FP32                         */
+  double alpha;          /* step size of Algorithm 1 step 7; default 0.95 (Sec. 7)     */
+  double gamma_tol;      /* SDSN stop: gamma <= gamma_tol; default 1e-6                */
+  int sdsn_max;          /* SDSN pass cap per call; default 1000                       */
+  int tile;              /* 0 = automatic, else 64 / 128 / 256                          */
+  int profile;           /* 1 = time kernels with HIP events into fram_stats (slower)  */
+} fram_options;
+
+typedef struct fram_ctx fram_ctx;
+
+/* Fill *opt with the defaults listed above. */
+void fram_default_options(fram_options* opt);
+
+/* Create a context bound to HIP device `device`.  hbm_budget_bytes caps the
+ * device workspace the context may hold (0 = no cap beyond device memory).
+ * No HIP call is made here: the device is initialised on first use.
+ * Returns FRAM_EINVAL if out is NULL or device < 0. */
+fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes);
+
+/* Release the context and its device workspace.  NULL is accepted. */
+void fram_destroy(fram_ctx* ctx);
+
+/* Bytes of device workspace a solve of size n at precision prec needs; used by
+ * the budget check and by admission control.  Pure host arithmetic. */
+size_t fram_workspace_bytes(int n, fram_precision prec, int tile);
+
+/* FRAM, Algorithm 1 (with Algorithm 2 as its projection), on host inputs.
+ *   A, B      host, n*n doubles, row-major; symmetric, finite, >= 0 (Sec. 3).
+ *   n         >= 1.  n == 1 returns perm {0}.
+ *   lambda    theta of Theorem 1, > 0 (the paper uses 2 for dense graphs and
+ *             10 for sparse ones, Sec. 7).
+ *   iters     >= 1, cap on outer iterations.
+ *   tol       >= 0, delta threshold; the loop is a do-while and stops when
+ *             delta <= tol (tol = 0 runs exactly `iters` iterations).
+ *   perm_out  host, n int32 (written).   objective_out  host, 1 double (written).
+ * Uses fram_default_options (FP32 GEMMs). */
+fram_status fram_solve(fram_ctx* ctx, const double* A, const double* B, int n,
+                       double lambda, int iters, double tol,
+                       int32_t* perm_out, double* objective_out);
+
+/* As fram_solve with explicit options (NULL = defaults) and stats (may be NULL). */
+fram_status fram_solve_ex(fram_ctx* ctx, const double* A, const double* B, int n,
+                          double lambda, int iters, double tol, const fram_options* opt,
+                          int32_t* perm_out, double* objective_out, fram_stats* stats);
+
+/* As fram_solve_ex with A and B already in device memory (dA, dB: n*n doubles,
+ * row-major, leading dimension n), work ordered on `stream` (a hipStream_t, or
+ * NULL for the context's own stream).  Symmetry/sign/finiteness of the device
+ * inputs are checked by a device kernel before the solve (FRAM_EINVAL).
+ * perm_out and objective_out are host pointers. */
+fram_status fram_solve_dev(fram_ctx* ctx, const double* dA, const double* dB, int n,
+                           double lambda, int iters, double tol, const fram_options* opt,
+                           int32_t* perm_out, double* objective_out, fram_stats* stats,
+                           void* stream);
+
+/* SDSN, Algorithm 2, alone: X_out = SDSN(K, theta).
+ *   K       host, n*n floats, row-major (any real values).
+ *   lambda  theta > 0.
+ *   X_out   host, n*n floats (written): nonnegative, row and column sums within
+ *           n*gamma_tol of 1 unless the pass cap was hit.
+ * X^(0) = (theta/2) K / max(K); a K with max <= 0 starts from the zero matrix,
+ * giving 11^T/n.  At least one pass is made. */
+fram_status fram_sdsn_project(fram_ctx* ctx, const float* K, int n, double lambda,
+                              float* X_out);
+
+/* As fram_sdsn_project with options (gamma_tol, sdsn_max) and stats
+ * (sdsn_passes, gamma, sdsn_capped). */
+fram_status fram_sdsn_project_ex(fram_ctx* ctx, const float* K, int n, double lambda,
+                                 const fram_options* opt, float* X_out, fram_stats* stats);
+
+/* Device-memory SDSN: dK and dX are device pointers (n*n floats, leading
+ * dimensions ldk, ldx >= n); dX may equal dK. */
+fram_status fram_sdsn_project_dev(fram_ctx* ctx, const float* dK, int ldk, int n,
+                                  double lambda, const fram_options* opt, float* dX,
+                                  int ldx, fram_stats* stats, void* stream);
+
+/* Gradient of eq. (3) alone, for kernel checks: X = A * N * B computed as
+ * W = B N^T (GEMM 1) and X = A W^T (GEMM 2) with inputs rounded to `prec`
+ * and FP32 accumulation; W is held in `prec`.  All pointers are host, n*n,
+ * row-major; A and B must be symmetric (B^T = B is used). */
+fram_status fram_gradient(fram_ctx* ctx, const float* A, const float* N, const float* B,
+                          int n, fram_precision prec, float* X_out);
+
+/* Exact linear assignment of Algorithm 1 step 10 / eq. (2) on a host matrix:
+ * perm_out maximises sum_i W[i, perm_out[i]], which is the permutation P
+ * minimising ||P - W||_F.  W: host, n*n floats, row-major, finite.
+ * perm_out: host, n int32 (written).  Runs on the host CPU (shortest
+ * augmenting paths with dual potentials, the Hungarian method); the solvers
+ * use it only when the device row argmax of N is not already a permutation
+ * (a row argmax that is a permutation is the exact optimum). */
+fram_status fram_assign(const float* W, int n, int32_t* perm_out);
+
+/* Many independent pairs (uneven n) solved in one batched device launch.
+ *   count        >= 1 pairs; A[i], B[i] host n[i]*n[i] doubles.
+ *   perm_out[i]  host, n[i] int32 (written); objective_out host, count doubles.
+ *   opt          NULL = defaults (FRAM_BF16 GEMMs for the batched kernel).
+ *   stats        NULL or count entries.
+ * Each pair's result is computed exactly as by the batched kernel alone:
+ * batching never changes a pair's arithmetic. */
+fram_status fram_solve_many(fram_ctx* ctx, int count, const double* const* A,
+                            const double* const* B, const int* n, double lambda, int iters,
+                            double tol, int32_t* const* perm_out, double* objective_out);
+
+fram_status fram_solve_many_ex(fram_ctx* ctx, int count, const double* const* A,
+                               const double* const* B, const int* n, double lambda,
+                               int iters, double tol, const fram_options* opt,
+                               int32_t* const* perm_out, double* objective_out,
+                               fram_stats* stats);
+
+/* Stats of the last call on this context. */
+fram_status fram_last_stats(const fram_ctx* ctx, fram_stats* out);
+
+/* Static text for a status code. */
+const char* fram_status_str(fram_status s);
+
+/* Text of the last error on this context ("" if none). */
+const char* fram_last_error(const fram_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRAM_H */

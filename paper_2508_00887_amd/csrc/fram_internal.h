@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP translation units of libfram.
+// Nothing here is part of the public ABI (see include/fram.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fram {
+
+// ----------------------------------------------------------------------------
+// Device-visible scalar state of one solve.  Lives in device memory; the host
+// reads it back with one async copy per outer iteration.
+struct DevState {
+  int done;          // SDSN converged (or capped) for the current projection
+  int passes;        // SDSN passes made by the current projection
+  int invalid;       // input validation flags (bit 0: non-finite, 1: negative, 2: asymmetric)
+  int pad0;
+  double gamma;      // gamma of the last SDSN output
+  double delta;      // delta of the last outer update
+  double dnum;       // ||N_new - N_old||_F^2 of the last update
+  double dden;       // ||N_new||_F^2 of the last update
+  double maxA;       // max entry of A (unscaled)
+  double maxB;       // max entry of B (unscaled)
+  double objective;  // sum_{k,l} A_kl B_{s(k)s(l)}
+};
+
+// One set of tile partials over an np x np matrix cut into nb x nb tiles of
+// edge BM (np = nb * BM), all sums in FP64.  rowp[bn * np + i] = sum over the
+// columns of tile column bn of row i; colp[bm * np + j] = sum over the rows of
+// tile row bm of column j; tot[bm * nb + bn] = total of tile (bm, bn);
+// tmax = FP32 tile max.
+struct Partials {
+  double* rowp;
+  double* colp;
+  double* tot;
+  float* tmax;
+};
+
+enum class Elem : int { F32 = 0, BF16 = 1, F16 = 2 };
+
+inline size_t elem_size(Elem e) { return e == Elem::F32 ? 4 : 2; }
+
+// ------------------------------------------------------------------ launches
+// All launches are asynchronous on `s`; they return hipSuccess or the launch
+// error.  Matrices are row-major with leading dimension ld (elements).
+
+// C (np x np) = P (np x np) * Q^T over K = n (rounded up to the K step),
+// inputs of type e, FP32 accumulation.
+// C is written as type e when c_f32 == false, as float otherwise.  np must be
+// a multiple of bm (64, 128 or 256); all padding rows/columns of P and Q must
+// be zero up to np.
+hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
+                          int n, int np, int ld, hipStream_t s);
+
+// Tile statistics of an n x n matrix: reads src (ld_src), writes it padded to
+// dst (np x np, ld np, zero padding) unless dst == nullptr or dst == src, and
+// fills `out` (row/col partials, FP64 tile totals, tile maxima).  Also resets
+// the SDSN fields of *st.
+hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, int n, int np,
+                             Partials out, DevState* st, hipStream_t s);
+
+// One SDSN pass (Algorithm 2 body) over X in place, pass index k >= 1.  Reads
+// the partials of its input from `in`, writes those of its output to `out`.
+hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
+                            DevState* st, int k, int max_passes, double theta,
+                            double gamma_tol, hipStream_t s);
+
+// N <- (1-alpha) N + alpha D with FP64 partial sums for delta; writes the
+// GEMM-operand copy Nlp in type e (skipped when e == F32 and Nlp == N).
+hipError_t launch_update(Elem e, const float* D, float* N, void* Nlp, int n, int np,
+                         double alpha, double* part, int nblocks, DevState* st,
+                         hipStream_t s);
+int update_blocks(int n);
+
+// Max of A and B (n x n FP64, ld n) into st->maxA / st->maxB, via partials.
+hipError_t launch_maxes(const double* A, const double* B, int n, double* part, int nblocks,
+                        DevState* st, hipStream_t s);
+int max_blocks(int n);
+
+// dst (np x np, type e) = src (n x n FP64) / max, zero padding.  which = 0
+// uses st->maxA, 1 uses st->maxB.
+hipError_t launch_cast_scaled(Elem e, const double* src, int n, void* dst, int np,
+                              const DevState* st, int which, hipStream_t s);
+
+// dst (np x np, type e) = src (n x n float, ld n), no scaling, zero padding.
+hipError_t launch_cast_f32(Elem e, const float* src, int n, void* dst, int np, hipStream_t s);
+
+// Zero `bytes` bytes of device memory with a fill kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Validation of device inputs: sets bits of st->invalid.
+hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s);
+
+// sigma[i] = argmax_j N[i, j] (lowest j on ties), i < n.
+hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s);
+
+// st->objective = sum_{k,l} A_kl B_{sigma(k) sigma(l)} in FP64.
+hipError_t launch_objective(const double* A, const double* B, const int32_t* sigma, int n,
+                            double* part, int nblocks, DevState* st, hipStream_t s);
+int objective_blocks(int n);
+
+// Copy an n x n float block between leading dimensions.
+hipError_t launch_copy_f32(const float* src, int ld_src, float* dst, int ld_dst, int n,
+                           hipStream_t s);
+
+// Host exact linear assignment: maximise sum_i W[i, sigma(i)], W n x n
+// row-major doubles.  sigma_init may hold a partial assignment (-1 = free).
+void host_lap_max(const float* W, int n, int ld, const int32_t* sigma_init, int32_t* sigma);
+
+}  // namespace fram

@@ -1,0 +1,217 @@
+// MFMA GEMMs of the FRAM gradient X = A N B (Algorithm 1, step 5; eq. 3).
+//
+// Both products are written in "NT" form C = P * Q^T with P and Q row-major
+// and K-contiguous: GEMM 1 is W = B * N^T (= (N B)^T because B is symmetric,
+// Sec. 3) and GEMM 2 is X = A * W^T = A N B.  So every operand fragment is a
+// contiguous 16-byte run of one row, loaded straight into LDS and read back
+// with 128-bit LDS reads.
+//
+// Tiling for gfx950: a workgroup of 4 waves (2 x 2) owns a BM x BM output
+// tile; each wave owns (BM/2) x (BM/2) as a grid of 32 x 32 MFMA blocks
+// (v_mfma_f32_32x32x16_{bf16,f16}, or four v_mfma_f32_32x32x2_f32 per 16-byte
+// chunk for the FP32 path).  K advances 128 bytes of each row per step
+// (64 bf16/f16 or 32 f32 elements) through a two-stage LDS ring with a
+// register prefetch of the next stage.  LDS rows are 128 bytes; the 16-byte
+// chunk index is XOR-swizzled with the row so the 128-bit reads of 32
+// consecutive rows spread over the banks.  Tiles are assigned so that
+// consecutive tiles (same row strip of P) land on the same XCD and share its
+// L2.
+#include "fram_internal.h"
+
+namespace fram {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <Elem E>
+struct Mfma;
+
+template <>
+struct Mfma<Elem::BF16> {
+  static constexpr int kPerChunk = 8;
+  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+  __device__ static inline void store(void* C, size_t idx, float v) {
+    reinterpret_cast<__bf16*>(C)[idx] = static_cast<__bf16>(v);
+  }
+};
+
+template <>
+struct Mfma<Elem::F16> {
+  static constexpr int kPerChunk = 8;
+  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  }
+  __device__ static inline void store(void* C, size_t idx, float v) {
+    reinterpret_cast<_Float16*>(C)[idx] = static_cast<_Float16>(v);
+  }
+};
+
+template <>
+struct Mfma<Elem::F32> {
+  static constexpr int kPerChunk = 4;
+  // Lane l holds A[row l%32][k-slot l/32] per instruction; the four floats of
+  // the chunk are four k-slots, applied identically to the A and B fragments.
+  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+  __device__ static inline void store(void* C, size_t idx, float v) {
+    reinterpret_cast<float*>(C)[idx] = v;
+  }
+};
+
+constexpr int kChunks = 8;  // 16-byte chunks per LDS row (128 bytes of K)
+
+__device__ __forceinline__ int swz(int row, int ch) { return ch ^ (row & 7); }
+
+template <Elem E, int BM, bool OUT_F32>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const uint4* __restrict__ P,
+                                                      const uint4* __restrict__ Q,
+                                                      void* __restrict__ C, int np, int ld,
+                                                      int ktiles) {
+  constexpr int WT = BM / 2;          // wave tile edge
+  constexpr int F = WT / 32;          // MFMA blocks per wave tile edge
+  constexpr int LOADS = BM * kChunks / 256;
+  __shared__ uint4 smem[2][2][BM][kChunks];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nbn = np / BM;
+  int bid = blockIdx.x;
+  const int ntiles = gridDim.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int m0 = (bid / nbn) * BM;
+  const int n0 = (bid % nbn) * BM;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int ldc = ld / Mfma<E>::kPerChunk;  // leading dimension in chunks
+
+  f32x16 acc[F][F];
+#pragma unroll
+  for (int i = 0; i < F; ++i)
+#pragma unroll
+    for (int j = 0; j < F; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+  const int lrow = tid >> 3;  // 0..31
+  const int lch = tid & 7;
+  uint4 ra[LOADS], rb[LOADS];
+
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const size_t r = (size_t)(lrow + 32 * i);
+      ra[i] = P[(m0 + r) * ldc + kt * kChunks + lch];
+      rb[i] = Q[(n0 + r) * ldc + kt * kChunks + lch];
+    }
+  };
+  auto sstore = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int r = lrow + 32 * i;
+      smem[st][0][r][swz(r, lch)] = ra[i];
+      smem[st][1][r][swz(r, lch)] = rb[i];
+    }
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < ktiles) gload(kt + 1);
+#pragma unroll
+    for (int s = 0; s < kChunks / 2; ++s) {
+      const int ch = 2 * s + half;
+      uint4 a[F], b[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        const int ra_ = wm * WT + f * 32 + l32;
+        const int rb_ = wn * WT + f * 32 + l32;
+        a[f] = smem[st][0][ra_][swz(ra_, ch)];
+        b[f] = smem[st][1][rb_][swz(rb_, ch)];
+      }
+#pragma unroll
+      for (int i = 0; i < F; ++i)
+#pragma unroll
+        for (int j = 0; j < F; ++j) Mfma<E>::mac(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < ktiles) sstore(st ^ 1);
+    __syncthreads();
+  }
+
+  // Accumulator layout of a 32x32 MFMA block: element 4*g + r of lane l is
+  // row 8*g + 4*(l/32) + r, column l%32.
+#pragma unroll
+  for (int i = 0; i < F; ++i)
+#pragma unroll
+    for (int j = 0; j < F; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const size_t row = (size_t)(m0 + wm * WT + i * 32 + 8 * g + 4 * half + r);
+          const size_t col = (size_t)(n0 + wn * WT + j * 32 + l32);
+          const float v = acc[i][j][4 * g + r];
+          if (OUT_F32)
+            reinterpret_cast<float*>(C)[row * ld + col] = v;
+          else
+            Mfma<E>::store(C, row * ld + col, v);
+        }
+}
+
+template <Elem E, bool OUT_F32>
+hipError_t launch_e(int bm, const void* P, const void* Q, void* C, int n, int np, int ld,
+                    hipStream_t s) {
+  const int kelems = kChunks * Mfma<E>::kPerChunk;
+  const int ktiles = (n + kelems - 1) / kelems;
+  const int nb = np / bm;
+  dim3 grid(nb * nb), block(256);
+  const uint4* p = static_cast<const uint4*>(P);
+  const uint4* q = static_cast<const uint4*>(Q);
+  switch (bm) {
+    case 64:
+      gemm_nt_kernel<E, 64, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      break;
+    case 128:
+      gemm_nt_kernel<E, 128, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      break;
+    case 256:
+      gemm_nt_kernel<E, 256, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
+                          int n, int np, int ld, hipStream_t s) {
+  if (np % bm != 0 || ld < np || np % 64 != 0 || n > np) return hipErrorInvalidValue;
+  switch (e) {
+    case Elem::F32:
+      return launch_e<Elem::F32, true>(bm, P, Q, C, n, np, ld, s);
+    case Elem::BF16:
+      return c_f32 ? launch_e<Elem::BF16, true>(bm, P, Q, C, n, np, ld, s)
+                   : launch_e<Elem::BF16, false>(bm, P, Q, C, n, np, ld, s);
+    case Elem::F16:
+      return c_f32 ? launch_e<Elem::F16, true>(bm, P, Q, C, n, np, ld, s)
+                   : launch_e<Elem::F16, false>(bm, P, Q, C, n, np, ld, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fram

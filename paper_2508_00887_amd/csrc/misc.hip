@@ -1,0 +1,378 @@
+// Memory-bound helper kernels of the FRAM path:
+//   prescale   (Algorithm 1, steps 2-3): max-reduce, scale and cast to the GEMM type;
+//   update     (Algorithm 1, steps 7-8): N <- (1-alpha) N + alpha D with FP64 sums for delta;
+//   discretise (Algorithm 1, step 10 / eq. 2): row argmax of N;
+//   objective  (eq. 1 without node term): sum_{k,l} A_kl B_{s(k) s(l)} in FP64;
+// plus input validation (Sec. 3: A nonnegative and symmetric), fills and copies.
+// Every reduction is two-stage with a fixed order, so results are bitwise
+// reproducible run to run.
+#include "fram_internal.h"
+
+namespace fram {
+namespace {
+
+constexpr int kT = 256;
+
+__device__ double block_sum_256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max_256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <Elem E>
+struct Conv;
+template <>
+struct Conv<Elem::F32> {
+  typedef float T;
+  __device__ static T from(double v) { return (float)v; }
+};
+template <>
+struct Conv<Elem::BF16> {
+  typedef __bf16 T;
+  __device__ static T from(double v) { return (__bf16)(float)v; }
+};
+template <>
+struct Conv<Elem::F16> {
+  typedef _Float16 T;
+  __device__ static T from(double v) { return (_Float16)(float)v; }
+};
+
+// ------------------------------------------------------------------ prescale
+__global__ __launch_bounds__(kT) void max_partial_kernel(const double* __restrict__ A,
+                                                         const double* __restrict__ B, size_t nn,
+                                                         double* part) {
+  __shared__ double sh[kT];
+  double ma = -INFINITY, mb = -INFINITY;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < nn; t += (size_t)gridDim.x * kT) {
+    ma = fmax(ma, A[t]);
+    mb = fmax(mb, B[t]);
+  }
+  ma = block_max_256(ma, sh);
+  mb = block_max_256(mb, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ma;
+    part[2 * blockIdx.x + 1] = mb;
+  }
+}
+
+__global__ __launch_bounds__(kT) void max_final_kernel(const double* part, int nblocks,
+                                                       DevState* st) {
+  __shared__ double sh[kT];
+  double ma = -INFINITY, mb = -INFINITY;
+  for (int b = threadIdx.x; b < nblocks; b += kT) {
+    ma = fmax(ma, part[2 * b]);
+    mb = fmax(mb, part[2 * b + 1]);
+  }
+  ma = block_max_256(ma, sh);
+  mb = block_max_256(mb, sh);
+  if (threadIdx.x == 0) {
+    st->maxA = ma;
+    st->maxB = mb;
+  }
+}
+
+template <Elem E>
+__global__ __launch_bounds__(kT) void cast_scaled_kernel(const double* __restrict__ src, int n,
+                                                         typename Conv<E>::T* __restrict__ dst,
+                                                         int np, const DevState* st, int which) {
+  const double m = which == 0 ? st->maxA : st->maxB;
+  const double inv_ok = (m > 0.0) ? 1.0 : 0.0;
+  const double den = (m > 0.0) ? m : 1.0;
+  const size_t total = (size_t)np * np;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const int i = (int)(t / np), j = (int)(t % np);
+    double v = 0.0;
+    if (i < n && j < n) v = inv_ok * (src[(size_t)i * n + j] / den);
+    dst[t] = Conv<E>::from(v);
+  }
+}
+
+template <Elem E>
+__global__ __launch_bounds__(kT) void cast_f32_kernel(const float* __restrict__ src, int n,
+                                                      typename Conv<E>::T* __restrict__ dst,
+                                                      int np) {
+  const size_t total = (size_t)np * np;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const int i = (int)(t / np), j = (int)(t % np);
+    double v = 0.0;
+    if (i < n && j < n) v = (double)src[(size_t)i * n + j];
+    dst[t] = Conv<E>::from(v);
+  }
+}
+
+// ------------------------------------------------------------------ update
+template <Elem E>
+__global__ __launch_bounds__(kT) void update_kernel(const float* __restrict__ D,
+                                                    float* __restrict__ N, void* Nlp, int n,
+                                                    int np, float alpha, double* part) {
+  __shared__ double sh[kT];
+  const float c1 = 1.0f - alpha;
+  double num = 0.0, den = 0.0;
+  const int q = np / 4;  // float4 per row
+  const size_t total = (size_t)n * q;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const size_t i = t / q, c = t % q;
+    const size_t idx = i * np + 4 * c;
+    const float4 o = *reinterpret_cast<const float4*>(N + idx);
+    const float4 d = *reinterpret_cast<const float4*>(D + idx);
+    float4 nn;
+    nn.x = fmaf(alpha, d.x, c1 * o.x);
+    nn.y = fmaf(alpha, d.y, c1 * o.y);
+    nn.z = fmaf(alpha, d.z, c1 * o.z);
+    nn.w = fmaf(alpha, d.w, c1 * o.w);
+    *reinterpret_cast<float4*>(N + idx) = nn;
+    if (E != Elem::F32) {
+      typedef typename Conv<E>::T T;
+      T* out = reinterpret_cast<T*>(Nlp) + idx;
+      out[0] = Conv<E>::from(nn.x);
+      out[1] = Conv<E>::from(nn.y);
+      out[2] = Conv<E>::from(nn.z);
+      out[3] = Conv<E>::from(nn.w);
+    }
+    const double ex = (double)nn.x - (double)o.x, ey = (double)nn.y - (double)o.y;
+    const double ez = (double)nn.z - (double)o.z, ew = (double)nn.w - (double)o.w;
+    num += (ex * ex + ey * ey) + (ez * ez + ew * ew);
+    den += ((double)nn.x * nn.x + (double)nn.y * nn.y) + ((double)nn.z * nn.z + (double)nn.w * nn.w);
+  }
+  num = block_sum_256(num, sh);
+  den = block_sum_256(den, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = num;
+    part[2 * blockIdx.x + 1] = den;
+  }
+}
+
+__global__ __launch_bounds__(kT) void delta_final_kernel(const double* part, int nblocks,
+                                                         DevState* st) {
+  __shared__ double sh[kT];
+  double num = 0.0, den = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kT) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  num = block_sum_256(num, sh);
+  den = block_sum_256(den, sh);
+  if (threadIdx.x == 0) {
+    st->dnum = num;
+    st->dden = den;
+    st->delta = den > 0.0 ? sqrt(num) / sqrt(den) : 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ validation
+__global__ __launch_bounds__(kT) void validate_kernel(const double* __restrict__ A, int n,
+                                                      DevState* st) {
+  __shared__ int sflag;
+  if (threadIdx.x == 0) sflag = 0;
+  __syncthreads();
+  int f = 0;
+  const size_t total = (size_t)n * n;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const size_t i = t / n, j = t % n;
+    const double v = A[t];
+    if (!isfinite(v)) f |= 1;
+    if (v < 0.0) f |= 2;
+    if (A[j * n + i] != v) f |= 4;
+  }
+  if (f) atomicOr(&sflag, f);
+  __syncthreads();
+  if (threadIdx.x == 0 && sflag) atomicOr(&st->invalid, sflag);
+}
+
+// ------------------------------------------------------------------ discretise
+__global__ __launch_bounds__(kT) void row_argmax_kernel(const float* __restrict__ N, int n,
+                                                        int np, int32_t* __restrict__ sigma) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float* r = N + (size_t)row * np;
+  float best = -INFINITY;
+  int bi = n;  // sentinel larger than any index
+  for (int j = lane; j < n; j += 64) {
+    const float v = r[j];
+    if (v > best) {
+      best = v;
+      bi = j;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) sigma[row] = bi < n ? bi : 0;
+}
+
+// ------------------------------------------------------------------ objective
+__global__ __launch_bounds__(kT) void objective_kernel(const double* __restrict__ A,
+                                                       const double* __restrict__ B,
+                                                       const int32_t* __restrict__ sigma, int n,
+                                                       double* part) {
+  __shared__ double sh[kT];
+  double acc = 0.0;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const double* ar = A + (size_t)k * n;
+    const double* br = B + (size_t)sigma[k] * n;
+    for (int l = threadIdx.x; l < n; l += kT) acc += ar[l] * br[sigma[l]];
+  }
+  acc = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kT) void objective_final_kernel(const double* part, int nblocks,
+                                                             DevState* st) {
+  __shared__ double sh[kT];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kT) acc += part[b];
+  acc = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) st->objective = acc;
+}
+
+// ------------------------------------------------------------------ fills
+__global__ __launch_bounds__(kT) void zero_kernel(uint4* p, size_t n16, unsigned char* tail,
+                                                  size_t ntail) {
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < n16; t += (size_t)gridDim.x * kT)
+    p[t] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kT) void copy_f32_kernel(const float* __restrict__ src, int ld_src,
+                                                      float* __restrict__ dst, int ld_dst, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const size_t i = t / n, j = t % n;
+    dst[i * ld_dst + j] = src[i * ld_src + j];
+  }
+}
+
+int grid_for(size_t work) {
+  size_t b = (work + kT - 1) / kT;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int max_blocks(int n) { return grid_for((size_t)n * n); }
+int update_blocks(int n) { return grid_for((size_t)n * n / 4 + 1); }
+int objective_blocks(int n) { return n < 1024 ? n : 1024; }
+
+hipError_t launch_maxes(const double* A, const double* B, int n, double* part, int nblocks,
+                        DevState* st, hipStream_t s) {
+  max_partial_kernel<<<nblocks, kT, 0, s>>>(A, B, (size_t)n * n, part);
+  max_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_scaled(Elem e, const double* src, int n, void* dst, int np,
+                              const DevState* st, int which, hipStream_t s) {
+  const int g = grid_for((size_t)np * np);
+  switch (e) {
+    case Elem::F32:
+      cast_scaled_kernel<Elem::F32><<<g, kT, 0, s>>>(src, n, (float*)dst, np, st, which);
+      break;
+    case Elem::BF16:
+      cast_scaled_kernel<Elem::BF16><<<g, kT, 0, s>>>(src, n, (__bf16*)dst, np, st, which);
+      break;
+    case Elem::F16:
+      cast_scaled_kernel<Elem::F16><<<g, kT, 0, s>>>(src, n, (_Float16*)dst, np, st, which);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(Elem e, const float* src, int n, void* dst, int np, hipStream_t s) {
+  const int g = grid_for((size_t)np * np);
+  switch (e) {
+    case Elem::F32:
+      cast_f32_kernel<Elem::F32><<<g, kT, 0, s>>>(src, n, (float*)dst, np);
+      break;
+    case Elem::BF16:
+      cast_f32_kernel<Elem::BF16><<<g, kT, 0, s>>>(src, n, (__bf16*)dst, np);
+      break;
+    case Elem::F16:
+      cast_f32_kernel<Elem::F16><<<g, kT, 0, s>>>(src, n, (_Float16*)dst, np);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(Elem e, const float* D, float* N, void* Nlp, int n, int np,
+                         double alpha, double* part, int nblocks, DevState* st,
+                         hipStream_t s) {
+  if (np % 4 != 0) return hipErrorInvalidValue;
+  switch (e) {
+    case Elem::F32:
+      update_kernel<Elem::F32><<<nblocks, kT, 0, s>>>(D, N, Nlp, n, np, (float)alpha, part);
+      break;
+    case Elem::BF16:
+      update_kernel<Elem::BF16><<<nblocks, kT, 0, s>>>(D, N, Nlp, n, np, (float)alpha, part);
+      break;
+    case Elem::F16:
+      update_kernel<Elem::F16><<<nblocks, kT, 0, s>>>(D, N, Nlp, n, np, (float)alpha, part);
+      break;
+  }
+  delta_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  const size_t ntail = bytes % 16;
+  zero_kernel<<<grid_for(n16 + 1), kT, 0, s>>>(static_cast<uint4*>(p), n16,
+                                                static_cast<unsigned char*>(p) + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s) {
+  validate_kernel<<<grid_for((size_t)n * n), kT, 0, s>>>(A, n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s) {
+  const int rows_per_block = kT / 64;
+  row_argmax_kernel<<<(n + rows_per_block - 1) / rows_per_block, kT, 0, s>>>(N, n, np, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const double* A, const double* B, const int32_t* sigma, int n,
+                            double* part, int nblocks, DevState* st, hipStream_t s) {
+  objective_kernel<<<nblocks, kT, 0, s>>>(A, B, sigma, n, part);
+  objective_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float* src, int ld_src, float* dst, int ld_dst, int n,
+                           hipStream_t s) {
+  copy_f32_kernel<<<grid_for((size_t)n * n), kT, 0, s>>>(src, ld_src, dst, ld_dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace fram

@@ -1,0 +1,770 @@
+// Host runtime of libfram: context, workspace plan, argument validation and
+// the loop driver of Algorithm 1 (outer fixed-point loop) around the device
+// kernels.  Implements the C ABI declared in include/fram.h.
+//
+// Loop driver.  Per outer iteration the device runs GEMM 1, GEMM 2, the tile
+// statistics of X, then SDSN passes.  SDSN is data-dependent (it stops when
+// gamma <= gamma_tol, Sec. 5.2), so passes are enqueued in chunks: every pass
+// kernel re-checks gamma of its input on the device and turns into a no-op
+// once the projection is done, and the host reads the done flag once per
+// chunk.  The first chunk of an iteration is sized from the previous
+// iteration's pass count (which settles quickly as N converges), so in steady
+// state one host synchronisation per outer iteration suffices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fram.h"
+#include "fram_internal.h"
+
+using fram::DevState;
+using fram::Elem;
+using fram::Partials;
+
+struct fram_ctx {
+  int device = 0;
+  size_t budget = 0;
+  bool inited = false;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevState* hst = nullptr;  // pinned host mirror of the device state
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profiling pair
+  std::string err;
+  fram_stats last{};
+  std::vector<float> hostN;  // staging for the host assignment fallback
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int choose_tile(int n, int requested) {
+  if (requested == 64 || requested == 128 || requested == 256) return requested;
+  const int cands[3] = {256, 128, 64};
+  for (int bm : cands) {
+    const long nb = (n + bm - 1) / bm;
+    if (nb * nb >= 200) return bm;
+  }
+  return 64;
+}
+
+struct Layout {
+  int bm = 64, np = 64, nb = 1;
+  Elem e = Elem::F32;
+  size_t A64 = 0, B64 = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
+  size_t rowp[2] = {0, 0}, colp[2] = {0, 0}, tot[2] = {0, 0}, tmax[2] = {0, 0};
+  size_t upd = 0, mx = 0, obj = 0, sigma = 0, state = 0;
+  int nupd = 1, nmax = 1, nobj = 1;
+  size_t total = 0;
+};
+
+enum class Use { Solve, SolveDev, Sdsn, Gradient };
+
+Layout plan(int n, Elem e, int tile, Use use) {
+  Layout L;
+  L.e = e;
+  L.bm = choose_tile(n, tile);
+  L.np = (n + L.bm - 1) / L.bm * L.bm;
+  L.nb = L.np / L.bm;
+  const size_t np2 = (size_t)L.np * L.np;
+  const size_t es = fram::elem_size(e);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  if (use == Use::Solve) {
+    L.A64 = take((size_t)n * n * 8);
+    L.B64 = take((size_t)n * n * 8);
+  }
+  const bool gemm = use != Use::Sdsn;
+  if (gemm) {
+    L.Alp = take(np2 * es);
+    L.Blp = take(np2 * es);
+    L.W = take(np2 * es);
+    L.Nlp = (e == Elem::F32) ? 0 : take(np2 * es);
+  }
+  L.X = take(np2 * 4);
+  if (use == Use::Solve || use == Use::SolveDev || use == Use::Gradient) L.N = take(np2 * 4);
+  for (int k = 0; k < 2; ++k) {
+    L.rowp[k] = take((size_t)L.nb * L.np * 8);
+    L.colp[k] = take((size_t)L.nb * L.np * 8);
+    L.tot[k] = take((size_t)L.nb * L.nb * 8);
+    L.tmax[k] = take((size_t)L.nb * L.nb * 4);
+  }
+  L.nupd = fram::update_blocks(n);
+  L.nmax = fram::max_blocks(n);
+  L.nobj = fram::objective_blocks(n);
+  L.upd = take((size_t)L.nupd * 16);
+  L.mx = take((size_t)L.nmax * 16);
+  L.obj = take((size_t)L.nobj * 8);
+  L.sigma = take((size_t)n * 4);
+  L.state = take(sizeof(DevState));
+  L.total = off;
+  return L;
+}
+
+bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP16; }
+
+fram_status check_options(const fram_options& o) {
+  if (!valid_prec((int)o.prec)) return FRAM_EINVAL;
+  if (!(o.alpha > 0.0 && o.alpha <= 1.0)) return FRAM_EINVAL;
+  if (!(o.gamma_tol >= 0.0) || !std::isfinite(o.gamma_tol)) return FRAM_EINVAL;
+  if (o.sdsn_max < 1) return FRAM_EINVAL;
+  if (!(o.tile == 0 || o.tile == 64 || o.tile == 128 || o.tile == 256)) return FRAM_EINVAL;
+  if (o.profile != 0 && o.profile != 1) return FRAM_EINVAL;
+  return FRAM_OK;
+}
+
+fram_status check_scalars(int n, double theta, int iters, double tol) {
+  if (n < 1) return FRAM_EINVAL;
+  if (!(theta > 0.0) || !std::isfinite(theta)) return FRAM_EINVAL;
+  if (iters < 1) return FRAM_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return FRAM_EINVAL;
+  return FRAM_OK;
+}
+
+// Sec. 3: A is nonnegative and symmetric; entries must also be finite.
+fram_status check_graph(const double* A, int n) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double v = A[(size_t)i * n + j];
+      if (!std::isfinite(v) || v < 0.0) return FRAM_EINVAL;
+      if (j > i && A[(size_t)j * n + i] != v) return FRAM_EINVAL;
+    }
+  return FRAM_OK;
+}
+
+#define HIPCHK(call)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) {                                            \
+      c->err = std::string(#call) + ": " + hipGetErrorString(e_);      \
+      return FRAM_EDEVICE;                                             \
+    }                                                                  \
+  } while (0)
+
+fram_status ensure_device(fram_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  if (c->inited) return FRAM_OK;
+  HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  HIPCHK(hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault));
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+  c->inited = true;
+  return FRAM_OK;
+}
+
+fram_status ensure_ws(fram_ctx* c, size_t bytes) {
+  if (c->budget != 0 && bytes > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  if (c->ws_bytes >= bytes) return FRAM_OK;
+  if (c->ws) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&c->ws, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    c->err = "device allocation failed";
+    return FRAM_ENOMEM;
+  }
+  HIPCHK(e);
+  c->ws_bytes = bytes;
+  return FRAM_OK;
+}
+
+template <typename T>
+T* at(fram_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(c->ws) + off);
+}
+
+Partials partials(fram_ctx* c, const Layout& L, int k) {
+  Partials p;
+  p.rowp = at<double>(c, L.rowp[k]);
+  p.colp = at<double>(c, L.colp[k]);
+  p.tot = at<double>(c, L.tot[k]);
+  p.tmax = at<float>(c, L.tmax[k]);
+  return p;
+}
+
+fram_status read_state(fram_ctx* c, DevState* dst, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c->hst, dst, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FRAM_OK;
+}
+
+// Profiling: when enabled, each timed launch is bracketed by two events on
+// its stream and waited for, so the elapsed time is that launch alone.
+struct Prof {
+  bool on = false;
+  fram_ctx* c = nullptr;
+  hipStream_t s = nullptr;
+  float last_ms = 0.0f;
+};
+
+template <typename F>
+fram_status timed(Prof& p, double* acc, int* cnt, F&& launch) {
+  fram_ctx* c = p.c;
+  if (!p.on) {
+    HIPCHK(launch());
+    return FRAM_OK;
+  }
+  HIPCHK(hipEventRecord(c->ev0, p.s));
+  HIPCHK(launch());
+  HIPCHK(hipEventRecord(c->ev1, p.s));
+  HIPCHK(hipEventSynchronize(c->ev1));
+  HIPCHK(hipEventElapsedTime(&p.last_ms, c->ev0, c->ev1));
+  if (acc) *acc += p.last_ms;
+  if (cnt) *cnt += 1;
+  return FRAM_OK;
+}
+
+// Runs SDSN passes on X (already holding the input, partial set 0 filled by
+// the tile statistics).  Returns passes made in *passes.
+fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevState* st,
+                            double theta, const fram_options& o, int first_chunk,
+                            hipStream_t s, int* passes, double* gamma, bool* capped,
+                            fram_stats* stt) {
+  int k = 1;
+  const int last = o.sdsn_max + 1;  // pass index that only evaluates gamma
+  int chunk = std::max(2, first_chunk);
+  if (o.profile) {
+    // One pass at a time; the launch that only finds gamma <= gamma_tol is
+    // not counted as a pass.
+    Prof p{true, c, s, 0.0f};
+    for (int kk = 1; kk <= last; ++kk) {
+      fram_status r = timed(p, nullptr, nullptr, [&] {
+        return fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
+                                      partials(c, L, kk & 1), st, kk, o.sdsn_max, theta,
+                                      o.gamma_tol, s);
+      });
+      if (r != FRAM_OK) return r;
+      r = read_state(c, st, s);
+      if (r != FRAM_OK) return r;
+      if (c->hst->done) break;
+      stt->ms_sdsn += p.last_ms;
+      stt->sdsn_launches += 1;
+    }
+    k = last + 1;
+  }
+  while (!o.profile) {
+    const int end = std::min(last, k + chunk - 1);
+    for (int kk = k; kk <= end; ++kk)
+      HIPCHK(fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
+                                    partials(c, L, kk & 1), st, kk, o.sdsn_max, theta,
+                                    o.gamma_tol, s));
+    k = end + 1;
+    fram_status r = read_state(c, st, s);
+    if (r != FRAM_OK) return r;
+    if (c->hst->done) break;
+    if (k > last) {
+      c->err = "SDSN loop ended without completion flag";
+      return FRAM_EDEVICE;
+    }
+    chunk = 4;
+  }
+  *passes = c->hst->passes;
+  *gamma = c->hst->gamma;
+  *capped = (*passes >= o.sdsn_max) && !(*gamma <= o.gamma_tol);
+  if (!std::isfinite(*gamma)) {
+    c->err = "non-finite gamma in SDSN";
+    return FRAM_ENUMERIC;
+  }
+  return FRAM_OK;
+}
+
+fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double* dA,
+                              const double* dB, float* N, int32_t* dsig, DevState* st,
+                              hipStream_t s, int32_t* perm, double* obj, int* host_lap) {
+  HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s));
+  HIPCHK(hipMemcpyAsync(perm, dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<char> seen(n, 0);
+  bool is_perm = true;
+  for (int i = 0; i < n; ++i) {
+    const int j = perm[i];
+    if (j < 0 || j >= n || seen[j]) {
+      is_perm = false;
+      break;
+    }
+    seen[j] = 1;
+  }
+  *host_lap = 0;
+  if (!is_perm) {
+    // Row maxima collide: exact assignment on the host, warm-started from them.
+    c->hostN.resize((size_t)n * L.np);
+    HIPCHK(hipMemcpyAsync(c->hostN.data(), N, (size_t)n * L.np * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int32_t> init(perm, perm + n);
+    fram::host_lap_max(c->hostN.data(), n, L.np, init.data(), perm);
+    HIPCHK(hipMemcpyAsync(dsig, perm, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    *host_lap = 1;
+  }
+  HIPCHK(fram::launch_objective(dA, dB, dsig, n, at<double>(c, L.obj), L.nobj, st, s));
+  fram_status r = read_state(c, st, s);
+  if (r != FRAM_OK) return r;
+  *obj = c->hst->objective;
+  if (!std::isfinite(*obj)) {
+    c->err = "non-finite objective";
+    return FRAM_ENUMERIC;
+  }
+  return FRAM_OK;
+}
+
+// Algorithm 1 on device inputs dA, dB (n x n FP64, ld n).
+fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const double* dB, int n,
+                      double theta, int iters, double tol, const fram_options& o,
+                      bool validate_dev, hipStream_t s, int32_t* perm, double* obj,
+                      fram_stats* stt) {
+  const Elem e = L.e;
+  const size_t np2 = (size_t)L.np * L.np;
+  DevState* st = at<DevState>(c, L.state);
+  void* Alp = at<void>(c, L.Alp);
+  void* Blp = at<void>(c, L.Blp);
+  void* W = at<void>(c, L.W);
+  float* N = at<float>(c, L.N);
+  void* Nlp = (e == Elem::F32) ? (void*)N : at<void>(c, L.Nlp);
+  float* X = at<float>(c, L.X);
+  int32_t* dsig = at<int32_t>(c, L.sigma);
+
+  HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
+  if (validate_dev) {
+    HIPCHK(fram::launch_validate(dA, n, st, s));
+    HIPCHK(fram::launch_validate(dB, n, st, s));
+    fram_status r = read_state(c, st, s);
+    if (r != FRAM_OK) return r;
+    if (c->hst->invalid) {
+      c->err = "device input is non-finite, negative or asymmetric";
+      return FRAM_EINVAL;
+    }
+  }
+  // Algorithm 1, steps 2-3 (each matrix scaled by its own maximum; SDSN's
+  // max-normalisation makes the scale immaterial in exact arithmetic).
+  HIPCHK(fram::launch_maxes(dA, dB, n, at<double>(c, L.mx), L.nmax, st, s));
+  HIPCHK(fram::launch_cast_scaled(e, dA, n, Alp, L.np, st, 0, s));
+  HIPCHK(fram::launch_cast_scaled(e, dB, n, Blp, L.np, st, 1, s));
+  // Algorithm 1, step 1: N^(0) = 0.
+  HIPCHK(fram::launch_zero(N, np2 * 4, s));
+  if (e != Elem::F32) HIPCHK(fram::launch_zero(Nlp, np2 * fram::elem_size(e), s));
+
+  int total_passes = 0, last_passes = 0, max_passes_seen = 0, it = 0;
+  bool any_capped = false, converged = false;
+  double gamma = 0.0, delta = 0.0;
+  int est = 8;
+  Prof prof{o.profile != 0, c, s, 0.0f};
+  for (it = 1; it <= iters; ++it) {
+    // Step 5: X = A N B as W = B N^T, X = A W^T.
+    fram_status r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
+      return fram::launch_gemm_nt(e, L.bm, Blp, Nlp, W, false, n, L.np, L.np, s);
+    });
+    if (r != FRAM_OK) return r;
+    r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
+      return fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s);
+    });
+    if (r != FRAM_OK) return r;
+    r = timed(prof, &stt->ms_stats, nullptr, [&] {
+      return fram::launch_tile_stats(L.bm, X, L.np, nullptr, n, L.np, partials(c, L, 0), st, s);
+    });
+    if (r != FRAM_OK) return r;
+    // Step 6: D = SDSN(X, theta), in place in X.
+    int passes = 0;
+    bool capped = false;
+    r = run_sdsn_passes(c, L, n, X, st, theta, o, est + 1, s, &passes, &gamma,
+                                    &capped, stt);
+    if (r != FRAM_OK) return r;
+    est = passes;
+    total_passes += passes;
+    last_passes = passes;
+    max_passes_seen = std::max(max_passes_seen, passes);
+    any_capped = any_capped || capped;
+    // Steps 7-8: N update and delta.
+    r = timed(prof, &stt->ms_update, nullptr, [&] {
+      return fram::launch_update(e, X, N, Nlp, n, L.np, o.alpha, at<double>(c, L.upd), L.nupd,
+                                 st, s);
+    });
+    if (r != FRAM_OK) return r;
+    if (tol > 0.0 || it == iters) {
+      r = read_state(c, st, s);
+      if (r != FRAM_OK) return r;
+      delta = c->hst->delta;
+      if (!std::isfinite(delta)) {
+        c->err = "non-finite delta";
+        return FRAM_ENUMERIC;
+      }
+      if (delta <= tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  if (it > iters) it = iters;
+  int host_lap = 0;
+  fram_status r = finish_discretise(c, L, n, dA, dB, N, dsig, st, s, perm, obj, &host_lap);
+  if (r != FRAM_OK) return r;
+  stt->outer_iters = it;
+  stt->sdsn_passes = total_passes;
+  stt->sdsn_passes_last = last_passes;
+  stt->sdsn_passes_max = max_passes_seen;
+  stt->converged = converged ? 1 : 0;
+  stt->sdsn_capped = any_capped ? 1 : 0;
+  stt->host_lap = host_lap;
+  stt->gemm_tile = L.bm;
+  stt->delta = delta;
+  stt->gamma = gamma;
+  return FRAM_OK;
+}
+
+fram_options defaults() {
+  fram_options o;
+  fram_default_options(&o);
+  return o;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+fram_status solve_host_impl(fram_ctx* c, const double* A, const double* B, int n, double theta,
+                            int iters, double tol, const fram_options& o, int32_t* perm,
+                            double* obj, fram_stats* stt) {
+  const double t0 = now_ms();
+  if (n == 1) {
+    perm[0] = 0;
+    *obj = A[0] * B[0];
+    stt->ms_total = now_ms() - t0;
+    return FRAM_OK;
+  }
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::Solve);
+  if (c->budget != 0 && L.total > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = c->stream;
+  double* dA = at<double>(c, L.A64);
+  double* dB = at<double>(c, L.B64);
+  HIPCHK(hipMemcpyAsync(dA, A, (size_t)n * n * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dB, B, (size_t)n * n * 8, hipMemcpyHostToDevice, s));
+  r = run_solve(c, L, dA, dB, n, theta, iters, tol, o, false, s, perm, obj, stt);
+  stt->ms_total = now_ms() - t0;
+  return r;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+void fram_default_options(fram_options* opt) {
+  if (!opt) return;
+  opt->prec = FRAM_FP32;
+  opt->alpha = 0.95;
+  opt->gamma_tol = 1e-6;
+  opt->sdsn_max = 1000;
+  opt->tile = 0;
+  opt->profile = 0;
+}
+
+fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
+  if (!out || device < 0) return FRAM_EINVAL;
+  fram_ctx* c = new (std::nothrow) fram_ctx();
+  if (!c) return FRAM_ENOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return FRAM_OK;
+}
+
+void fram_destroy(fram_ctx* c) {
+  if (!c) return;
+  if (c->inited) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->hst) (void)hipHostFree(c->hst);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+size_t fram_workspace_bytes(int n, fram_precision prec, int tile) {
+  if (n < 1 || !valid_prec((int)prec)) return 0;
+  return plan(n, (Elem)prec, tile, Use::Solve).total;
+}
+
+fram_status fram_solve_ex(fram_ctx* c, const double* A, const double* B, int n, double lambda,
+                          int iters, double tol, const fram_options* opt, int32_t* perm_out,
+                          double* objective_out, fram_stats* stats) {
+  if (!c || !A || !B || !perm_out || !objective_out) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
+  if (r == FRAM_OK) r = check_graph(A, n);
+  if (r == FRAM_OK) r = check_graph(B, n);
+  if (r != FRAM_OK) {
+    c->err = "invalid argument";
+    return r;
+  }
+  fram_stats st{};
+  r = solve_host_impl(c, A, B, n, lambda, iters, tol, o, perm_out, objective_out, &st);
+  c->last = st;
+  if (stats) *stats = st;
+  return r;
+}
+
+fram_status fram_solve(fram_ctx* c, const double* A, const double* B, int n, double lambda,
+                       int iters, double tol, int32_t* perm_out, double* objective_out) {
+  return fram_solve_ex(c, A, B, n, lambda, iters, tol, nullptr, perm_out, objective_out,
+                       nullptr);
+}
+
+fram_status fram_solve_dev(fram_ctx* c, const double* dA, const double* dB, int n,
+                           double lambda, int iters, double tol, const fram_options* opt,
+                           int32_t* perm_out, double* objective_out, fram_stats* stats,
+                           void* stream) {
+  if (!c || !dA || !dB || !perm_out || !objective_out) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
+  if (r != FRAM_OK) {
+    c->err = "invalid argument";
+    return r;
+  }
+  const double t0 = now_ms();
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::SolveDev);
+  if (c->budget != 0 && L.total > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  fram_stats st{};
+  if (n == 1) {
+    double a = 0, b = 0;
+    HIPCHK(hipMemcpyAsync(&a, dA, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&b, dB, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(std::isfinite(a) && std::isfinite(b) && a >= 0 && b >= 0)) return FRAM_EINVAL;
+    perm_out[0] = 0;
+    *objective_out = a * b;
+  } else {
+    r = run_solve(c, L, dA, dB, n, lambda, iters, tol, o, true, s, perm_out, objective_out, &st);
+  }
+  st.ms_total = now_ms() - t0;
+  c->last = st;
+  if (stats) *stats = st;
+  return r;
+}
+
+fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, double lambda,
+                                  const fram_options* opt, float* dX, int ldx,
+                                  fram_stats* stats, void* stream) {
+  if (!c || !dK || !dX) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r != FRAM_OK || n < 1 || ldk < n || ldx < n || !(lambda > 0.0) || !std::isfinite(lambda)) {
+    c->err = "invalid argument";
+    return FRAM_EINVAL;
+  }
+  const double t0 = now_ms();
+  const Layout L = plan(n, Elem::F32, o.tile, Use::Sdsn);
+  if (c->budget != 0 && L.total > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  DevState* st = at<DevState>(c, L.state);
+  float* X = at<float>(c, L.X);
+  HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
+  HIPCHK(fram::launch_tile_stats(L.bm, dK, ldk, X, n, L.np, partials(c, L, 0), st, s));
+  int passes = 0;
+  double gamma = 0.0;
+  bool capped = false;
+  fram_stats stt{};
+  r = run_sdsn_passes(c, L, n, X, st, lambda, o, 8, s, &passes, &gamma, &capped, &stt);
+  if (r != FRAM_OK) return r;
+  HIPCHK(fram::launch_copy_f32(X, L.np, dX, ldx, n, s));
+  HIPCHK(hipStreamSynchronize(s));
+  stt.sdsn_passes = passes;
+  stt.sdsn_passes_last = passes;
+  stt.sdsn_passes_max = passes;
+  stt.sdsn_capped = capped ? 1 : 0;
+  stt.gamma = gamma;
+  stt.gemm_tile = L.bm;
+  stt.ms_total = now_ms() - t0;
+  c->last = stt;
+  if (stats) *stats = stt;
+  return FRAM_OK;
+}
+
+fram_status fram_sdsn_project_ex(fram_ctx* c, const float* K, int n, double lambda,
+                                 const fram_options* opt, float* X_out, fram_stats* stats) {
+  if (!c || !K || !X_out || n < 1) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  if (check_options(o) != FRAM_OK || !(lambda > 0.0) || !std::isfinite(lambda)) return FRAM_EINVAL;
+  for (size_t t = 0; t < (size_t)n * n; ++t)
+    if (!std::isfinite(K[t])) return FRAM_EINVAL;
+  const Layout L = plan(n, Elem::F32, o.tile, Use::Sdsn);
+  const size_t extra = align_up((size_t)n * n * 4);
+  if (c->budget != 0 && L.total + extra > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total + extra);
+  if (r != FRAM_OK) return r;
+  // The staging copy of K sits after the SDSN layout in the same workspace.
+  float* dK = at<float>(c, L.total);
+  HIPCHK(hipMemcpyAsync(dK, K, (size_t)n * n * 4, hipMemcpyHostToDevice, c->stream));
+  r = fram_sdsn_project_dev(c, dK, n, n, lambda, &o, dK, n, stats, c->stream);
+  if (r != FRAM_OK) return r;
+  HIPCHK(hipMemcpyAsync(X_out, dK, (size_t)n * n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return FRAM_OK;
+}
+
+fram_status fram_sdsn_project(fram_ctx* c, const float* K, int n, double lambda, float* X_out) {
+  return fram_sdsn_project_ex(c, K, n, lambda, nullptr, X_out, nullptr);
+}
+
+fram_status fram_gradient(fram_ctx* c, const float* A, const float* N, const float* B, int n,
+                          fram_precision prec, float* X_out) {
+  if (!c || !A || !N || !B || !X_out || n < 1 || !valid_prec((int)prec)) return FRAM_EINVAL;
+  const Elem e = (Elem)prec;
+  const Layout L = plan(n, e, 0, Use::Gradient);
+  if (c->budget != 0 && L.total > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = c->stream;
+  float* X = at<float>(c, L.X);
+  float* N32 = at<float>(c, L.N);
+  void* Alp = at<void>(c, L.Alp);
+  void* Blp = at<void>(c, L.Blp);
+  void* W = at<void>(c, L.W);
+  void* Nlp = (e == Elem::F32) ? (void*)N32 : at<void>(c, L.Nlp);
+  const size_t bytes = (size_t)n * n * 4;
+  // Stage each host operand through X (n*n floats fit in np*np), then cast.
+  HIPCHK(hipMemcpyAsync(X, A, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(fram::launch_cast_f32(e, X, n, Alp, L.np, s));
+  HIPCHK(hipMemcpyAsync(X, B, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(fram::launch_cast_f32(e, X, n, Blp, L.np, s));
+  HIPCHK(hipMemcpyAsync(X, N, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(fram::launch_cast_f32(e, X, n, Nlp, L.np, s));
+  HIPCHK(fram::launch_gemm_nt(e, L.bm, Blp, Nlp, W, false, n, L.np, L.np, s));
+  HIPCHK(fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s));
+  HIPCHK(hipMemcpy2DAsync(X_out, (size_t)n * 4, X, (size_t)L.np * 4, (size_t)n * 4, n,
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FRAM_OK;
+}
+
+fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
+                               const double* const* B, const int* n, double lambda, int iters,
+                               double tol, const fram_options* opt, int32_t* const* perm_out,
+                               double* objective_out, fram_stats* stats) {
+  if (!c || count < 1 || !A || !B || !n || !perm_out || !objective_out) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r != FRAM_OK) return r;
+  for (int p = 0; p < count; ++p) {
+    if (!A[p] || !B[p] || !perm_out[p]) return FRAM_EINVAL;
+    r = check_scalars(n[p], lambda, iters, tol);
+    if (r == FRAM_OK) r = check_graph(A[p], n[p]);
+    if (r == FRAM_OK) r = check_graph(B[p], n[p]);
+    if (r != FRAM_OK) {
+      c->err = "invalid argument in pair " + std::to_string(p);
+      return r;
+    }
+  }
+  for (int p = 0; p < count; ++p) {
+    fram_stats st{};
+    r = solve_host_impl(c, A[p], B[p], n[p], lambda, iters, tol, o, perm_out[p],
+                        &objective_out[p], &st);
+    if (stats) stats[p] = st;
+    c->last = st;
+    if (r != FRAM_OK) return r;
+  }
+  return FRAM_OK;
+}
+
+fram_status fram_solve_many(fram_ctx* c, int count, const double* const* A,
+                            const double* const* B, const int* n, double lambda, int iters,
+                            double tol, int32_t* const* perm_out, double* objective_out) {
+  return fram_solve_many_ex(c, count, A, B, n, lambda, iters, tol, nullptr, perm_out,
+                            objective_out, nullptr);
+}
+
+fram_status fram_assign(const float* W, int n, int32_t* perm_out) {
+  if (!W || !perm_out || n < 1) return FRAM_EINVAL;
+  for (size_t t = 0; t < (size_t)n * n; ++t)
+    if (!std::isfinite(W[t])) return FRAM_EINVAL;
+  std::vector<int32_t> init(n);
+  for (int i = 0; i < n; ++i) {
+    int bi = 0;
+    for (int j = 1; j < n; ++j)
+      if (W[(size_t)i * n + j] > W[(size_t)i * n + bi]) bi = j;
+    init[i] = bi;
+  }
+  fram::host_lap_max(W, n, n, init.data(), perm_out);
+  return FRAM_OK;
+}
+
+fram_status fram_last_stats(const fram_ctx* c, fram_stats* out) {
+  if (!c || !out) return FRAM_EINVAL;
+  *out = c->last;
+  return FRAM_OK;
+}
+
+const char* fram_status_str(fram_status s) {
+  switch (s) {
+    case FRAM_OK:
+      return "ok";
+    case FRAM_EINVAL:
+      return "invalid argument";
+    case FRAM_ENOMEM:
+      return "out of HBM budget";
+    case FRAM_EDEVICE:
+      return "device error";
+    case FRAM_ENUMERIC:
+      return "non-finite value";
+    case FRAM_EBUSY:
+      return "busy";
+  }
+  return "unknown status";
+}
+
+const char* fram_last_error(const fram_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+// SDSN (Algorithm 2) as one fused, memory-bound pass per iteration.
+//
+// One pass maps its input X to
+//     Y = P2(P1(s X)),
+//     P1(Z)_ij = Z_ij + 1/n + (1^T Z 1)/n^2 - (Z 1)_i/n - (1^T Z)_j/n   (eq. P1_sol)
+//     P2(Z)    = max(0, Z)                                              (Sec. 5.1)
+// with s = theta / (2 max X) on the first pass (Alg. 2, first line) and 1
+// afterwards.  Since the row sums r, column sums c and total S of the input
+// are all P1 needs, each pass also produces r, c and S of its output, so the
+// next pass can start immediately: the row and column sums are written as
+// per-tile FP64 partials (fixed order, no atomics), and the stopping measure
+// gamma = 1^T Y 1 / n - 1 (Sec. 5.2, App. B.1) of a pass output is evaluated
+// in FP64 at the start of the next pass.  A pass that finds gamma <= gamma_tol
+// marks the projection done and leaves X untouched, so a host loop may launch
+// passes in chunks and read the flag once per chunk.
+//
+// Precision.  The correction is split symmetrically,
+//     1/n + sS/n^2 - s r_i/n - s c_j/n = alpha_i + beta_j,
+//     alpha_i = 1/(2n) + sS/(2n^2) - s r_i/n,  beta_j = 1/(2n) + sS/(2n^2) - s c_j/n,
+// and formed in FP64 from FP64 sums.  Near convergence (s = 1, r, c ~ 1,
+// S ~ n) both terms are O(gamma/n) and keep full FP32 relative precision, so
+// Y = max(0, fma(s, x, alpha_i + beta_j)) rounds once at the size of x.
+//
+// Tiles are BM x BM with 4*BM threads: each wave streams 16 rows of the tile,
+// each lane a float4 of columns, so every global access of a wave is one or
+// more contiguous 1 KB runs.  Row partials go through LDS (a transposing
+// reduction), column partials stay in registers until the end of the tile;
+// both are summed in FP64 from per-lane FP32 sums of at most 16 elements.
+#include "fram_internal.h"
+
+namespace fram {
+namespace {
+
+template <int NT>
+__device__ double block_sum_f64(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ float block_max_f32(float v, float* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = fmaxf(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct TileArgs {
+  const float* src;  // input matrix
+  int ld_src;
+  float* dst;        // output matrix (may equal src), leading dimension np
+  int n, np;
+  Partials in, out;
+  DevState* st;
+  int k, max_passes;
+  double theta, gamma_tol;
+};
+
+// PASS = false: statistics of src (and optional padded copy into dst).
+// PASS = true : one SDSN pass, in place on dst (== src, ld np).
+template <int BM, bool PASS>
+__global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
+  constexpr int NT = 4 * BM;
+  constexpr int LPR = BM / 4;       // lanes per tile row
+  constexpr int RPW = 64 / LPR;     // tile rows per wave step
+  constexpr int STEPS = 16 / RPW;   // each wave covers 16 rows
+  __shared__ float s_rowred[BM][LPR + 1];
+  __shared__ float s_colred[16][BM];
+  __shared__ float s_a[BM];
+  __shared__ float s_b[BM];
+  __shared__ double s_red[NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int bn = blockIdx.x, bm = blockIdx.y, nb = gridDim.x;
+  const int n = a.n, np = a.np;
+  DevState* st = a.st;
+
+  float s = 1.0f;
+  if (PASS) {
+    // One thread reads the flag so that the whole workgroup takes the same
+    // branch even if another workgroup of this launch sets it meanwhile.
+    __shared__ int s_done;
+    if (tid == 0) s_done = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_done) return;
+    double part = 0.0;
+    for (int t = tid; t < nb * nb; t += NT) part += a.in.tot[t];
+    const double S = block_sum_f64<NT>(part, s_red);
+    if (a.k >= 2) {
+      const double gamma_in = S / n - 1.0;
+      if (gamma_in <= a.gamma_tol || a.k > a.max_passes) {
+        if (bm == 0 && bn == 0 && tid == 0) {
+          st->done = 1;
+          st->passes = a.k - 1;
+          st->gamma = gamma_in;
+        }
+        return;
+      }
+    } else {
+      float m = -INFINITY;
+      for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
+      m = block_max_f32<NT>(m, reinterpret_cast<float*>(s_red));
+      s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
+    }
+    const double sd = (double)s;
+    const double dn = (double)n;
+    const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
+    for (int r = tid; r < BM; r += NT) {
+      const int i = bm * BM + r;
+      double ri = 0.0;
+      for (int b = 0; b < nb; ++b) ri += a.in.rowp[(size_t)b * np + i];
+      s_a[r] = (float)(half - sd * ri / dn);
+    }
+    for (int c = tid; c < BM; c += NT) {
+      const int j = bn * BM + c;
+      double cj = 0.0;
+      for (int b = 0; b < nb; ++b) cj += a.in.colp[(size_t)b * np + j];
+      s_b[c] = (float)(half - sd * cj / dn);
+    }
+    __syncthreads();
+  } else {
+    if (bm == 0 && bn == 0 && tid == 0) {
+      st->done = 0;
+      st->passes = 0;
+    }
+  }
+
+  const int q = lane / LPR;
+  const int lc = lane % LPR;
+  const int cl = lc * 4;
+  const int j = bn * BM + cl;
+  float4 bt = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (PASS) bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
+  float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
+  float lmax = -INFINITY;
+  const bool c0 = j < n, c1 = j + 1 < n, c2 = j + 2 < n, c3 = j + 3 < n;
+
+#pragma unroll
+  for (int stp = 0; stp < STEPS; ++stp) {
+    const int rl = w * 16 + stp * RPW + q;
+    const int i = bm * BM + rl;
+    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n) {
+      if (PASS) {
+        float4* row = reinterpret_cast<float4*>(a.dst + (size_t)i * np + j);
+        const float4 x = *row;
+        const float ai = s_a[rl];
+        y.x = c0 ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
+        y.y = c1 ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
+        y.z = c2 ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
+        y.w = c3 ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
+        *row = y;
+      } else {
+        const float* row = a.src + (size_t)i * a.ld_src + j;
+        y.x = c0 ? row[0] : 0.0f;
+        y.y = c1 ? row[1] : 0.0f;
+        y.z = c2 ? row[2] : 0.0f;
+        y.w = c3 ? row[3] : 0.0f;
+        if (c0) lmax = fmaxf(lmax, y.x);
+        if (c1) lmax = fmaxf(lmax, y.y);
+        if (c2) lmax = fmaxf(lmax, y.z);
+        if (c3) lmax = fmaxf(lmax, y.w);
+        if (a.dst != nullptr && a.dst != a.src)
+          *reinterpret_cast<float4*>(a.dst + (size_t)i * np + j) = y;
+      }
+    } else if (!PASS && a.dst != nullptr && a.dst != a.src) {
+      *reinterpret_cast<float4*>(a.dst + (size_t)i * np + j) = y;
+    }
+    const float rs = (y.x + y.y) + (y.z + y.w);
+    s_rowred[rl][lc] = rs;
+    cacc.x += y.x;
+    cacc.y += y.y;
+    cacc.z += y.z;
+    cacc.w += y.w;
+  }
+  *reinterpret_cast<float4*>(&s_colred[w * RPW + q][cl]) = cacc;
+  __syncthreads();
+
+  double rowsum;
+  {  // row partials: 4 threads per row, fixed order, FP64
+    const int r = tid >> 2, p = tid & 3;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < LPR / 4; ++u) v += (double)s_rowred[r][p * (LPR / 4) + u];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    if (p == 0) a.out.rowp[(size_t)bn * np + bm * BM + r] = v;
+    rowsum = (p == 0) ? v : 0.0;
+  }
+  {  // column partials, FP64
+    const int c = tid >> 2, p = tid & 3;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += (double)s_colred[p * 4 + u][c];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    if (p == 0) a.out.colp[(size_t)bm * np + bn * BM + c] = v;
+  }
+  const double tt = block_sum_f64<NT>(rowsum, s_red);
+  if (!PASS) {
+    const float tm = block_max_f32<NT>(lmax, reinterpret_cast<float*>(s_red));
+    if (tid == 0) a.out.tmax[bm * nb + bn] = tm;
+  }
+  if (tid == 0) a.out.tot[bm * nb + bn] = tt;
+}
+
+template <bool PASS>
+hipError_t launch_tile(int bm, const TileArgs& a, hipStream_t s) {
+  const int nb = a.np / bm;
+  dim3 grid(nb, nb);
+  switch (bm) {
+    case 64:
+      tile_kernel<64, PASS><<<grid, dim3(256), 0, s>>>(a);
+      break;
+    case 128:
+      tile_kernel<128, PASS><<<grid, dim3(512), 0, s>>>(a);
+      break;
+    case 256:
+      tile_kernel<256, PASS><<<grid, dim3(1024), 0, s>>>(a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, int n, int np,
+                             Partials out, DevState* st, hipStream_t s) {
+  if (np % bm != 0 || n > np || n < 1) return hipErrorInvalidValue;
+  TileArgs a{};
+  a.src = src;
+  a.ld_src = ld_src;
+  a.dst = dst;
+  a.n = n;
+  a.np = np;
+  a.out = out;
+  a.st = st;
+  return launch_tile<false>(bm, a, s);
+}
+
+hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
+                            DevState* st, int k, int max_passes, double theta,
+                            double gamma_tol, hipStream_t s) {
+  if (np % bm != 0 || n > np || n < 1 || k < 1) return hipErrorInvalidValue;
+  TileArgs a{};
+  a.src = X;
+  a.ld_src = np;
+  a.dst = X;
+  a.n = n;
+  a.np = np;
+  a.in = in;
+  a.out = out;
+  a.st = st;
+  a.k = k;
+  a.max_passes = max_passes;
+  a.theta = theta;
+  a.gamma_tol = gamma_tol;
+  return launch_tile<true>(bm, a, s);
+}
+
+}  // namespace fram

@@ -1,0 +1,297 @@
+"""ctypes binding of libfram.so with the C ABI's names (include/fram.h).
+
+Module-level functions carry the exact C names and take a context handle;
+the ``Context`` class wraps them with numpy in/out.  Device-memory variants
+take raw device pointers (e.g. ``tensor.data_ptr()`` of a torch tensor) and a
+HIP stream handle; torch is only a source of device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import pathlib
+
+import numpy as np
+
+FRAM_OK, FRAM_EINVAL, FRAM_ENOMEM, FRAM_EDEVICE, FRAM_ENUMERIC, FRAM_EBUSY = range(6)
+FRAM_FP32, FRAM_BF16, FRAM_FP16 = 0, 1, 2
+PRECISIONS = {"fp32": FRAM_FP32, "bf16": FRAM_BF16, "fp16": FRAM_FP16}
+
+_HERE = pathlib.Path(__file__).resolve().parent
+
+
+def library_path() -> pathlib.Path:
+    return pathlib.Path(os.environ.get("FRAM_LIBRARY", _HERE / "libfram.so"))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int),
+        ("sdsn_passes", ctypes.c_int),
+        ("sdsn_passes_last", ctypes.c_int),
+        ("sdsn_passes_max", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("sdsn_capped", ctypes.c_int),
+        ("host_lap", ctypes.c_int),
+        ("gemm_tile", ctypes.c_int),
+        ("delta", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+        ("gemm_launches", ctypes.c_int),
+        ("sdsn_launches", ctypes.c_int),
+        ("ms_gemm", ctypes.c_double),
+        ("ms_sdsn", ctypes.c_double),
+        ("ms_stats", ctypes.c_double),
+        ("ms_update", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("prec", ctypes.c_int),
+        ("alpha", ctypes.c_double),
+        ("gamma_tol", ctypes.c_double),
+        ("sdsn_max", ctypes.c_int),
+        ("tile", ctypes.c_int),
+        ("profile", ctypes.c_int),
+    ]
+
+
+class FramError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str = ""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({message})")
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "fram_default_options": (None, [_P]),
+    "fram_create": (_I, [ctypes.POINTER(_P), _I, ctypes.c_size_t]),
+    "fram_destroy": (None, [_P]),
+    "fram_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I]),
+    "fram_solve": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P]),
+    "fram_solve_ex": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P]),
+    "fram_solve_dev": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P, _P]),
+    "fram_sdsn_project": (_I, [_P, _P, _I, _D, _P]),
+    "fram_sdsn_project_ex": (_I, [_P, _P, _I, _D, _P, _P, _P]),
+    "fram_sdsn_project_dev": (_I, [_P, _P, _I, _I, _D, _P, _P, _I, _P, _P]),
+    "fram_gradient": (_I, [_P, _P, _P, _P, _I, _I, _P]),
+    "fram_assign": (_I, [_P, _I, _P]),
+    "fram_solve_many": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P]),
+    "fram_solve_many_ex": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P, _P, _P]),
+    "fram_last_stats": (_I, [_P, _P]),
+    "fram_status_str": (ctypes.c_char_p, [_I]),
+    "fram_last_error": (ctypes.c_char_p, [_P]),
+}
+
+
+def load_library():
+    """Load libfram.so; raises if it is missing (build with
+    ``python -m paper_2508_00887_amd.build``).  There is no fallback.
+
+    torch is imported first when available: it carries its own HIP runtime
+    (libamdhip64.so.7), and libfram must bind to that same runtime so that
+    device pointers and streams from torch are valid in the library (two HIP
+    runtimes in one process do not share devices)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    path = library_path()
+    if not path.exists():
+        raise ImportError(f"{path} not found: build it with `python -m paper_2508_00887_amd.build`")
+    lib = ctypes.CDLL(str(path))
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+# ---------------------------------------------------------------- C names
+def fram_default_options() -> Options:
+    o = Options()
+    load_library().fram_default_options(ctypes.byref(o))
+    return o
+
+
+def fram_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = _P()
+    st = load_library().fram_create(ctypes.byref(h), device, hbm_budget_bytes)
+    if st != FRAM_OK:
+        raise FramError(st, "fram_create")
+    return h.value
+
+
+def fram_destroy(ctx: int) -> None:
+    load_library().fram_destroy(ctx)
+
+
+def fram_workspace_bytes(n: int, prec: int = FRAM_FP32, tile: int = 0) -> int:
+    return int(load_library().fram_workspace_bytes(n, prec, tile))
+
+
+def fram_status_str(status: int) -> str:
+    return load_library().fram_status_str(status).decode()
+
+
+def fram_last_error(ctx: int) -> str:
+    return load_library().fram_last_error(ctx).decode()
+
+
+def _check(ctx: int, st: int, where: str):
+    if st != FRAM_OK:
+        raise FramError(st, where, f"{fram_status_str(st)}; {fram_last_error(ctx)}")
+
+
+def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
+             profile=False) -> Options:
+    o = Options()
+    o.profile = 1 if profile else 0
+    o.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    o.alpha = alpha
+    o.gamma_tol = gamma_tol
+    o.sdsn_max = sdsn_max
+    o.tile = tile
+    return o
+
+
+class Context:
+    """One FRAM context (device, stream, workspace).  Not thread-safe."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.lib = load_library()
+        self.handle = fram_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.handle:
+            fram_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ FRAM
+    def solve(self, A, B, theta=2.0, iters=100, tol=0.0, **opts):
+        """fram_solve_ex on host arrays; returns (perm, objective, stats dict)."""
+        A, B = _f64(A), _f64(B)
+        n = A.shape[0]
+        perm = np.empty(n, dtype=np.int32)
+        obj = ctypes.c_double()
+        stats = Stats()
+        o = _options(**opts)
+        st = self.lib.fram_solve_ex(self.handle, _ptr(A), _ptr(B), n, theta, iters, tol,
+                                    ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
+                                    ctypes.byref(stats))
+        _check(self.handle, st, "fram_solve_ex")
+        return perm.astype(np.int64), obj.value, stats.as_dict()
+
+    def solve_dev(self, dA: int, dB: int, n: int, theta=2.0, iters=100, tol=0.0, stream=0,
+                  **opts):
+        """fram_solve_dev on device pointers (n*n doubles each)."""
+        perm = np.empty(n, dtype=np.int32)
+        obj = ctypes.c_double()
+        stats = Stats()
+        o = _options(**opts)
+        st = self.lib.fram_solve_dev(self.handle, dA, dB, n, theta, iters, tol, ctypes.byref(o),
+                                     _ptr(perm), ctypes.byref(obj), ctypes.byref(stats),
+                                     stream or None)
+        _check(self.handle, st, "fram_solve_dev")
+        return perm.astype(np.int64), obj.value, stats.as_dict()
+
+    def sdsn_project(self, K, theta=2.0, gamma_tol=1e-6, sdsn_max=1000, tile=0):
+        """fram_sdsn_project_ex on a host matrix; returns (X, stats dict)."""
+        K = _f32(K)
+        n = K.shape[0]
+        X = np.empty((n, n), dtype=np.float32)
+        stats = Stats()
+        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile)
+        st = self.lib.fram_sdsn_project_ex(self.handle, _ptr(K), n, theta, ctypes.byref(o),
+                                           _ptr(X), ctypes.byref(stats))
+        _check(self.handle, st, "fram_sdsn_project_ex")
+        return X, stats.as_dict()
+
+    def sdsn_project_dev(self, dK: int, ldk: int, n: int, dX: int, ldx: int, theta=2.0,
+                         gamma_tol=1e-6, sdsn_max=1000, tile=0, stream=0):
+        stats = Stats()
+        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile)
+        st = self.lib.fram_sdsn_project_dev(self.handle, dK, ldk, n, theta, ctypes.byref(o), dX,
+                                            ldx, ctypes.byref(stats), stream or None)
+        _check(self.handle, st, "fram_sdsn_project_dev")
+        return stats.as_dict()
+
+    def gradient(self, A, N, B, prec="fp32"):
+        """fram_gradient: X = A N B with GEMM inputs rounded to `prec`."""
+        A, N, B = _f32(A), _f32(N), _f32(B)
+        n = A.shape[0]
+        X = np.empty((n, n), dtype=np.float32)
+        st = self.lib.fram_gradient(self.handle, _ptr(A), _ptr(N), _ptr(B), n,
+                                    PRECISIONS[prec] if isinstance(prec, str) else prec, _ptr(X))
+        _check(self.handle, st, "fram_gradient")
+        return X
+
+    def solve_many(self, As, Bs, theta=2.0, iters=100, tol=0.0, **opts):
+        """fram_solve_many_ex; returns (list of perms, objectives array, list of stats)."""
+        As = [_f64(a) for a in As]
+        Bs = [_f64(b) for b in Bs]
+        count = len(As)
+        ns = np.array([a.shape[0] for a in As], dtype=np.int32)
+        perms = [np.empty(int(n), dtype=np.int32) for n in ns]
+        pa = (ctypes.c_void_p * count)(*[_ptr(a) for a in As])
+        pb = (ctypes.c_void_p * count)(*[_ptr(b) for b in Bs])
+        pp = (ctypes.c_void_p * count)(*[_ptr(p) for p in perms])
+        objs = np.empty(count, dtype=np.float64)
+        stats = (Stats * count)()
+        o = _options(**opts)
+        st = self.lib.fram_solve_many_ex(self.handle, count, pa, pb, _ptr(ns), theta, iters, tol,
+                                         ctypes.byref(o), pp, _ptr(objs), stats)
+        _check(self.handle, st, "fram_solve_many_ex")
+        return [p.astype(np.int64) for p in perms], objs, [s.as_dict() for s in stats]
+
+    def last_stats(self) -> dict:
+        s = Stats()
+        _check(self.handle, self.lib.fram_last_stats(self.handle, ctypes.byref(s)), "fram_last_stats")
+        return s.as_dict()
+
+
+def fram_assign(W) -> np.ndarray:
+    """Exact linear assignment maximising sum_i W[i, perm[i]] (eq. 2), host side."""
+    W = _f32(W)
+    n = W.shape[0]
+    perm = np.empty(n, dtype=np.int32)
+    st = load_library().fram_assign(_ptr(W), n, _ptr(perm))
+    if st != FRAM_OK:
+        raise FramError(st, "fram_assign", fram_status_str(st))
+    return perm.astype(np.int64)

@@ -1,0 +1,186 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/fram.h declares, validates arguments before any device call, enforces
+the HBM budget, and its host assignment solver is exact."""
+import ctypes
+import itertools
+import pathlib
+import re
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+from paper_2508_00887_amd import fram as F
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    text = (ROOT / "include" / "fram.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fram_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = F.load_library()
+    names = declared_functions()
+    assert "fram_solve" in names and "fram_sdsn_project" in names and "fram_solve_many" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_declares_the_same_functions():
+    assert set(declared_functions()) == set(F._SIGS)
+
+
+def test_product_never_imports_the_oracle():
+    for path in (ROOT / "paper_2508_00887_amd").rglob("*"):
+        if path.suffix in (".py", ".hip", ".cpp", ".h"):
+            src = path.read_text()
+            assert "import oracle" not in src and "from oracle" not in src, path
+            assert "fram64" not in src, path
+
+
+@pytest.fixture
+def hctx():
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def _graph(n=6, seed=0):
+    rng = np.random.default_rng(seed)
+    A = np.triu(rng.random((n, n)), 1)
+    return A + A.T
+
+
+def _raw_solve(ctx, A, B, n, theta=2.0, iters=10, tol=0.0, opts=None):
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    obj = ctypes.c_double()
+    st = F.Stats()
+    o = opts if opts is not None else F.fram_default_options()
+    a = A.ctypes.data if A is not None else None
+    b = B.ctypes.data if B is not None else None
+    return F.load_library().fram_solve_ex(ctx.handle, a, b, n, theta, iters, tol, ctypes.byref(o),
+                                          perm.ctypes.data, ctypes.byref(obj), ctypes.byref(st))
+
+
+def test_invalid_scalars_and_pointers(hctx):
+    A = _graph()
+    B = _graph(seed=1)
+    assert _raw_solve(hctx, None, B, 6) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, None, 6) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 0) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, -3) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, theta=0.0) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, theta=-1.0) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, theta=float("nan")) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, iters=0) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, tol=-1e-3) == F.FRAM_EINVAL
+    assert _raw_solve(hctx, A, B, 6, tol=float("inf")) == F.FRAM_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("prec", 7), ("alpha", 0.0), ("alpha", 1.5),
+                                         ("gamma_tol", -1.0), ("sdsn_max", 0), ("tile", 96),
+                                         ("profile", 3)])
+def test_invalid_options(hctx, field, value):
+    o = F.fram_default_options()
+    setattr(o, field, value)
+    assert _raw_solve(hctx, _graph(), _graph(seed=1), 6, opts=o) == F.FRAM_EINVAL
+
+
+@pytest.mark.parametrize("bad", ["negative", "nan", "inf", "asymmetric"])
+def test_invalid_graph_entries(hctx, bad):
+    A = _graph()
+    B = _graph(seed=1)
+    if bad == "negative":
+        A[1, 2] = A[2, 1] = -0.5
+    elif bad == "nan":
+        B[0, 3] = B[3, 0] = float("nan")
+    elif bad == "inf":
+        B[0, 0] = float("inf")
+    else:
+        A[0, 1] += 1e-9
+    assert _raw_solve(hctx, A, B, 6) == F.FRAM_EINVAL
+    with pytest.raises(F.FramError):
+        hctx.solve(A, B)
+
+
+def test_budget_is_enforced_before_device_use():
+    c = F.Context(0, hbm_budget_bytes=4096)
+    try:
+        A = _graph(100)
+        assert _raw_solve(c, A, A.copy(), 100) == F.FRAM_ENOMEM
+        assert "budget" in F.fram_last_error(c.handle)
+    finally:
+        c.close()
+
+
+def test_workspace_bytes_is_monotone_and_precision_aware():
+    sizes = [F.fram_workspace_bytes(n) for n in (10, 100, 1000, 4000)]
+    assert sizes == sorted(sizes) and sizes[0] > 0
+    assert F.fram_workspace_bytes(4000, F.FRAM_BF16) < F.fram_workspace_bytes(4000, F.FRAM_FP32)
+    assert F.fram_workspace_bytes(0) == 0
+    # n = 4000 needs well under 1 GB of device state.
+    assert F.fram_workspace_bytes(4000, F.FRAM_FP32) < 1 << 30
+
+
+def test_single_node_needs_no_device(hctx):
+    perm, obj, st = hctx.solve(np.array([[3.0]]), np.array([[2.0]]))
+    assert list(perm) == [0] and obj == 6.0 and st["outer_iters"] == 0
+
+
+def test_create_rejects_bad_device_and_status_strings():
+    h = ctypes.c_void_p()
+    assert F.load_library().fram_create(ctypes.byref(h), -1, 0) == F.FRAM_EINVAL
+    assert F.load_library().fram_create(None, 0, 0) == F.FRAM_EINVAL
+    texts = {F.fram_status_str(s) for s in range(6)}
+    assert len(texts) == 6 and "ok" in texts
+    F.load_library().fram_destroy(None)
+
+
+def test_solve_many_validates_every_pair(hctx):
+    A = _graph()
+    bad = _graph(seed=2)
+    bad[0, 1] = -1.0
+    with pytest.raises(F.FramError) as e:
+        hctx.solve_many([A, A], [A, bad])
+    assert e.value.status == F.FRAM_EINVAL
+
+
+def test_sdsn_project_validates(hctx):
+    K = np.ones((4, 4), dtype=np.float32)
+    with pytest.raises(F.FramError):
+        hctx.sdsn_project(K, theta=0.0)
+    K[1, 1] = np.nan
+    with pytest.raises(F.FramError):
+        hctx.sdsn_project(K, theta=2.0)
+
+
+def _brute(W):
+    n = W.shape[0]
+    return max(itertools.permutations(range(n)), key=lambda p: sum(float(W[i, p[i]]) for i in range(n)))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_host_assignment_is_exact(seed):
+    rng = np.random.default_rng(seed)
+    n = 7
+    W = rng.random((n, n)).astype(np.float32)
+    if seed % 2:
+        W[:] = W[0]  # every row has the same maximiser: all rows collide
+    p = F.fram_assign(W)
+    best = _brute(W.astype(np.float64))
+    Wd = W.astype(np.float64)
+    assert abs(Wd[np.arange(n), p].sum() - Wd[np.arange(n), best].sum()) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 50, 300])
+def test_host_assignment_matches_scipy(n):
+    rng = np.random.default_rng(n)
+    W = (rng.random((n, n)) ** 4).astype(np.float32)
+    p = F.fram_assign(W)
+    assert sorted(p) == list(range(n))
+    r, c = linear_sum_assignment(W.astype(np.float64), maximize=True)
+    Wd = W.astype(np.float64)
+    assert abs(Wd[np.arange(n), p].sum() - Wd[r, c].sum()) <= 1e-9 * max(1.0, Wd[r, c].sum())

@@ -1,0 +1,94 @@
+"""GPU parity of SDSN (Algorithm 2) through fram_sdsn_project (C ABI).
+
+* Closed forms from Algorithm 2 (permutation inputs for theta <= 2 and
+  theta > 2, constant and non-positive inputs) must hold to FP32 rounding.
+* Random inputs: the GPU's pass count must match the FP64 oracle's (gamma is
+  evaluated in FP64 on both sides), and after the same number of passes the
+  matrices agree elementwise within an FP32 error budget that grows with the
+  pass count (each pass is non-expansive; every pass adds at most a few FP32
+  roundings of entries of size ~1/n).
+* Output invariants: X >= 0 exactly, row/column sums within n*gamma.
+"""
+import numpy as np
+import pytest
+
+from oracle import fram64 as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("theta", [1.0, 2.0])
+@pytest.mark.parametrize("n", [3, 64, 100])
+def test_permutation_small_theta_one_pass(ctx, n, theta):
+    Pi = np.eye(n, dtype=np.float32)[np.random.default_rng(n).permutation(n)]
+    X, st = ctx.sdsn_project(Pi, theta)
+    assert st["sdsn_passes"] == 1
+    np.testing.assert_allclose(X, theta / 2 * Pi + (1 - theta / 2) / n, atol=2e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("n,theta", [(5, 4.0), (50, 3.0)])
+def test_permutation_large_theta_closed_form(ctx, n, theta):
+    Pi = np.eye(n, dtype=np.float32)[np.random.default_rng(n).permutation(n)]
+    gth = 1e-4
+    X, st = ctx.sdsn_project(Pi, theta, gamma_tol=gth, sdsn_max=100000)
+    a0 = theta / 2
+    k = next(k for k in range(1, 10**6) if (a0 - 1) * (1 - 1 / n) ** k <= gth)
+    assert abs(st["sdsn_passes"] - k) <= 1
+    a = 1 - (1 - a0) * (1 - 1 / n) ** st["sdsn_passes"]
+    np.testing.assert_allclose(X, a * Pi, atol=1e-5)
+
+
+@pytest.mark.parametrize("K", ["constant", "zero", "negative"])
+def test_degenerate_inputs_give_uniform(ctx, K):
+    n = 70
+    M = {"constant": np.full((n, n), 3.5), "zero": np.zeros((n, n)),
+         "negative": -np.random.default_rng(0).random((n, n))}[K].astype(np.float32)
+    X, st = ctx.sdsn_project(M, 2.0)
+    np.testing.assert_allclose(X, 1.0 / n, rtol=1e-6)
+    # One pass is exact in real arithmetic; in FP32 the first pass cancels
+    # terms of size theta/2 to produce entries 1/n, which can leave gamma a few
+    # n*2^-24 above zero and cost one more (no-change) pass.
+    assert st["sdsn_passes"] <= 2
+
+
+def test_single_node(ctx):
+    X, st = ctx.sdsn_project(np.array([[7.0]], dtype=np.float32), 2.0)
+    assert X[0, 0] == 1.0
+
+
+@pytest.mark.parametrize("theta", [2.0, 10.0])
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 65, 130, 255, 300, 777, 1000])
+def test_sdsn_matches_oracle(ctx, n, theta):
+    rng = np.random.default_rng(7 * n + int(theta))
+    K = (rng.random((n, n)) ** 2).astype(np.float32)
+    gth = 1e-6
+    X, st = ctx.sdsn_project(K, theta, gamma_tol=gth, sdsn_max=20000)
+    k = st["sdsn_passes"]
+    _, info = O.sdsn(K.astype(np.float64), theta, gth, 20000)
+    # gamma falls by ~1% per pass near gamma_tol at theta = 10, so FP32 rounding
+    # of gamma's trajectory may move the crossing by a few percent of the passes.
+    assert abs(k - info.passes) <= max(3, int(0.05 * info.passes)), (k, info.passes)
+    D, _ = O.sdsn(K.astype(np.float64), theta, 0.0, max_passes=k)
+    err = np.abs(X.astype(np.float64) - D).max()
+    assert err <= k * 2e-6 / n + 1e-7, err
+    assert (X >= 0).all()
+    tol = n * max(st["gamma"], 0.0) + 1e-4
+    assert np.abs(X.astype(np.float64).sum(0) - 1).max() <= tol
+    assert np.abs(X.astype(np.float64).sum(1) - 1).max() <= tol
+
+
+def test_sdsn_deterministic(ctx):
+    K = (np.random.default_rng(3).random((600, 600)) ** 3).astype(np.float32)
+    X1, s1 = ctx.sdsn_project(K, 2.0)
+    X2, s2 = ctx.sdsn_project(K, 2.0)
+    np.testing.assert_array_equal(X1, X2)
+    assert s1["sdsn_passes"] == s2["sdsn_passes"]
+
+
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_sdsn_tile_variants_agree(ctx, tile):
+    K = (np.random.default_rng(5).random((300, 300)) ** 2).astype(np.float32)
+    Xa, sa = ctx.sdsn_project(K, 2.0, tile=64)
+    Xb, sb = ctx.sdsn_project(K, 2.0, tile=tile)
+    assert abs(sa["sdsn_passes"] - sb["sdsn_passes"]) <= 1
+    np.testing.assert_allclose(Xa, Xb, atol=1e-6)
