@@ -14,8 +14,11 @@ namespace fram {
 struct DevState {
   int done;          // SDSN converged (or capped) for the current projection
   int passes;        // SDSN passes made by the current projection
-  int invalid;       // input validation flags (bit 0: non-finite, 1: negative, 2: asymmetric)
-  int pad0;
+  int invalid;       // flags: 1 non-finite, 2 negative, 4 asymmetric input; 8 barrier timeout
+  int total_passes;  // passes summed over projections (on-chip SDSN path)
+  int max_passes;    // largest pass count of one projection (on-chip SDSN path)
+  int capped;        // some projection hit the pass cap (on-chip SDSN path)
+  int pad0, pad1;
   double gamma;      // gamma of the last SDSN output
   double delta;      // delta of the last outer update
   double dnum;       // ||N_new - N_old||_F^2 of the last update
@@ -65,6 +68,37 @@ hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, i
 hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
                             DevState* st, int k, int max_passes, double theta,
                             double gamma_tol, hipStream_t s);
+
+// Arguments of the on-chip SDSN projection (sdsn_persistent.hip).
+struct PersistArgs {
+  const float* src;  // input matrix, leading dimension ld_src
+  int ld_src;
+  int src_vec;       // 1: rows of src are 16-byte aligned (float4 loads)
+  float* dst;        // optional: final D, np x np (ld np); nullptr to skip
+  int n, np;
+  Partials p[2];     // ping-pong partial sets (set 0 also gets tile maxima)
+  DevState* st;
+  unsigned long long* flags;      // grid barrier: gridDim.x + 1 epoch flags
+  unsigned long long epoch_base;  // larger than every epoch of earlier launches
+  int max_passes;
+  int spin_limit;    // bound on each barrier wait (sleep iterations)
+  double theta, gamma_tol;
+  float* N;          // optional fused update: N <- (1-alpha) N + alpha D
+  void* Nlp;         // GEMM-type copy of N (nlp_kind 1 = bf16, 2 = f16, 0 = none)
+  int nlp_kind;
+  float alpha;
+  double* dpart;     // FP64 delta partials, 2 per workgroup (tile order)
+};
+
+// True if one cooperative launch of nb*nb workgroups of the BM variant fits
+// on `device` (all workgroups co-resident).
+bool sdsn_persistent_fits(int device, int bm, int np);
+
+// Every SDSN pass of one projection in one cooperative launch (grid nb*nb).
+hipError_t launch_sdsn_persistent(int bm, const PersistArgs& a, hipStream_t s);
+
+// st->delta from `nblocks` pairs of FP64 partial sums (num, den).
+hipError_t launch_delta_final(const double* part, int nblocks, DevState* st, hipStream_t s);
 
 // N <- (1-alpha) N + alpha D with FP64 partial sums for delta; writes the
 // GEMM-operand copy Nlp in type e (skipped when e == F32 and Nlp == N).

@@ -343,6 +343,11 @@ hipError_t launch_update(Elem e, const float* D, float* N, void* Nlp, int n, int
   return hipGetLastError();
 }
 
+hipError_t launch_delta_final(const double* part, int nblocks, DevState* st, hipStream_t s) {
+  delta_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;
   const size_t ntail = bytes % 16;

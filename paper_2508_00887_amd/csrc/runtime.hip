@@ -38,11 +38,15 @@ struct fram_ctx {
   std::string err;
   fram_stats last{};
   std::vector<float> hostN;  // staging for the host assignment fallback
+  int fit_bm = 0, fit_np = 0, fit_ok = 0;  // cached on-chip SDSN feasibility
+  unsigned long long launches = 0;         // on-chip launches (barrier epochs)
+  unsigned long long* flags = nullptr;     // grid-barrier flags, zeroed once, own allocation
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr size_t kFlagBytes = 8 * 1024;  // >= 8 * (max on-chip grid + 1)
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int choose_tile(int n, int requested) {
@@ -103,7 +107,7 @@ Layout plan(int n, Elem e, int tile, Use use) {
   L.nupd = fram::update_blocks(n);
   L.nmax = fram::max_blocks(n);
   L.nobj = fram::objective_blocks(n);
-  L.upd = take((size_t)L.nupd * 16);
+  L.upd = take((size_t)std::max(L.nupd, L.nb * L.nb) * 16);
   L.mx = take((size_t)L.nmax * 16);
   L.obj = take((size_t)L.nobj * 8);
   L.sigma = take((size_t)n * 4);
@@ -121,6 +125,7 @@ fram_status check_options(const fram_options& o) {
   if (o.sdsn_max < 1) return FRAM_EINVAL;
   if (!(o.tile == 0 || o.tile == 64 || o.tile == 128 || o.tile == 256)) return FRAM_EINVAL;
   if (o.profile != 0 && o.profile != 1) return FRAM_EINVAL;
+  if (o.sdsn_mode < 0 || o.sdsn_mode > 2) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -159,6 +164,11 @@ fram_status ensure_device(fram_ctx* c) {
   HIPCHK(hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault));
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
+  // Barrier flags of the on-chip SDSN launches: a fixed allocation, zeroed
+  // once; epochs only grow, so stale flags are always below the next epoch.
+  HIPCHK(hipMalloc((void**)&c->flags, kFlagBytes));
+  HIPCHK(fram::launch_zero(c->flags, kFlagBytes, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   c->inited = true;
   return FRAM_OK;
 }
@@ -286,6 +296,70 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
   return FRAM_OK;
 }
 
+// Decide whether the on-chip SDSN path is used for this layout.
+fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool* on) {
+  *on = false;
+  if (o.sdsn_mode == 1) return FRAM_OK;
+  if (o.sdsn_max > (1 << 24) - 8) {  // barrier epochs of one launch must stay below 2^24
+    if (o.sdsn_mode == 2) {
+      c->err = "sdsn_max too large for the on-chip SDSN path";
+      return FRAM_EINVAL;
+    }
+    return FRAM_OK;
+  }
+  if ((size_t)L.nb * L.nb + 1 > kFlagBytes / sizeof(unsigned long long)) {
+    if (o.sdsn_mode == 2) {
+      c->err = "too many tiles for the on-chip SDSN path";
+      return FRAM_EINVAL;
+    }
+    return FRAM_OK;
+  }
+  if (c->fit_bm != L.bm || c->fit_np != L.np) {
+    c->fit_bm = L.bm;
+    c->fit_np = L.np;
+    c->fit_ok = fram::sdsn_persistent_fits(c->device, L.bm, L.np) ? 1 : 0;
+  }
+  if (!c->fit_ok && o.sdsn_mode == 2) {
+    c->err = "on-chip SDSN does not fit this device";
+    return FRAM_EINVAL;
+  }
+  *on = c->fit_ok != 0;
+  return FRAM_OK;
+}
+
+constexpr int kSpinLimit = 1 << 25;
+
+// One on-chip projection: D = SDSN(src) with every pass in one cooperative
+// launch; optionally writes D to dst (ld np) and/or applies the N update.
+fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* src, int ld_src,
+                            float* dst, float* N, void* Nlp, Elem e, double alpha,
+                            DevState* st, double theta, const fram_options& o, hipStream_t s) {
+  fram::PersistArgs a{};
+  a.src = src;
+  a.ld_src = ld_src;
+  a.src_vec = (ld_src % 4 == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0) ? 1 : 0;
+  a.dst = dst;
+  a.n = n;
+  a.np = L.np;
+  a.p[0] = partials(c, L, 0);
+  a.p[1] = partials(c, L, 1);
+  a.st = st;
+  a.flags = c->flags;
+  a.epoch_base = (++c->launches) << 24;
+  a.max_passes = o.sdsn_max;
+  a.spin_limit = kSpinLimit;
+  a.theta = theta;
+  a.gamma_tol = o.gamma_tol;
+  a.N = N;
+  a.Nlp = (e == Elem::F32) ? nullptr : Nlp;
+  a.nlp_kind = (N == nullptr || e == Elem::F32) ? 0 : (e == Elem::BF16 ? 1 : 2);
+  a.alpha = (float)alpha;
+  a.dpart = at<double>(c, L.upd);
+  HIPCHK(fram::launch_sdsn_persistent(L.bm, a, s));
+  if (N != nullptr) HIPCHK(fram::launch_delta_final(a.dpart, L.nb * L.nb, st, s));
+  return FRAM_OK;
+}
+
 fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double* dA,
                               const double* dB, float* N, int32_t* dsig, DevState* st,
                               hipStream_t s, int32_t* perm, double* obj, int* host_lap) {
@@ -365,6 +439,11 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   double gamma = 0.0, delta = 0.0;
   int est = 8;
   Prof prof{o.profile != 0, c, s, 0.0f};
+  bool onchip = false;
+  {
+    fram_status q = use_onchip(c, L, o, &onchip);
+    if (q != FRAM_OK) return q;
+  }
   for (it = 1; it <= iters; ++it) {
     // Step 5: X = A N B as W = B N^T, X = A W^T.
     fram_status r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
@@ -375,30 +454,49 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       return fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s);
     });
     if (r != FRAM_OK) return r;
-    r = timed(prof, &stt->ms_stats, nullptr, [&] {
-      return fram::launch_tile_stats(L.bm, X, L.np, nullptr, n, L.np, partials(c, L, 0), st, s);
-    });
-    if (r != FRAM_OK) return r;
-    // Step 6: D = SDSN(X, theta), in place in X.
-    int passes = 0;
-    bool capped = false;
-    r = run_sdsn_passes(c, L, n, X, st, theta, o, est + 1, s, &passes, &gamma,
-                                    &capped, stt);
-    if (r != FRAM_OK) return r;
-    est = passes;
-    total_passes += passes;
-    last_passes = passes;
-    max_passes_seen = std::max(max_passes_seen, passes);
-    any_capped = any_capped || capped;
-    // Steps 7-8: N update and delta.
-    r = timed(prof, &stt->ms_update, nullptr, [&] {
-      return fram::launch_update(e, X, N, Nlp, n, L.np, o.alpha, at<double>(c, L.upd), L.nupd,
-                                 st, s);
-    });
-    if (r != FRAM_OK) return r;
+    if (onchip) {
+      // Steps 6-8 in one cooperative launch (+ the delta reduction).
+      r = timed(prof, &stt->ms_sdsn, nullptr, [&] {
+        fram_status q = run_sdsn_onchip(c, L, n, X, L.np, nullptr, N, Nlp, e, o.alpha, st,
+                                        theta, o, s);
+        return q == FRAM_OK ? hipSuccess : hipErrorUnknown;
+      });
+      if (r != FRAM_OK) return r;
+      if (prof.on) {
+        r = read_state(c, st, s);
+        if (r != FRAM_OK) return r;
+        stt->sdsn_launches += c->hst->passes;
+      }
+    } else {
+      r = timed(prof, &stt->ms_stats, nullptr, [&] {
+        return fram::launch_tile_stats(L.bm, X, L.np, nullptr, n, L.np, partials(c, L, 0), st,
+                                       s);
+      });
+      if (r != FRAM_OK) return r;
+      // Step 6: D = SDSN(X, theta), in place in X.
+      int passes = 0;
+      bool capped = false;
+      r = run_sdsn_passes(c, L, n, X, st, theta, o, est + 1, s, &passes, &gamma, &capped, stt);
+      if (r != FRAM_OK) return r;
+      est = passes;
+      total_passes += passes;
+      last_passes = passes;
+      max_passes_seen = std::max(max_passes_seen, passes);
+      any_capped = any_capped || capped;
+      // Steps 7-8: N update and delta.
+      r = timed(prof, &stt->ms_update, nullptr, [&] {
+        return fram::launch_update(e, X, N, Nlp, n, L.np, o.alpha, at<double>(c, L.upd),
+                                   L.nupd, st, s);
+      });
+      if (r != FRAM_OK) return r;
+    }
     if (tol > 0.0 || it == iters) {
       r = read_state(c, st, s);
       if (r != FRAM_OK) return r;
+      if (c->hst->invalid & 8) {
+        c->err = "on-chip SDSN barrier timed out";
+        return FRAM_EDEVICE;
+      }
       delta = c->hst->delta;
       if (!std::isfinite(delta)) {
         c->err = "non-finite delta";
@@ -414,6 +512,22 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   int host_lap = 0;
   fram_status r = finish_discretise(c, L, n, dA, dB, N, dsig, st, s, perm, obj, &host_lap);
   if (r != FRAM_OK) return r;
+  if (onchip) {
+    // finish_discretise left the device state in c->hst.
+    if (c->hst->invalid & 8) {
+      c->err = "on-chip SDSN barrier timed out";
+      return FRAM_EDEVICE;
+    }
+    total_passes = c->hst->total_passes;
+    max_passes_seen = c->hst->max_passes;
+    last_passes = c->hst->passes;
+    any_capped = c->hst->capped != 0;
+    gamma = c->hst->gamma;
+    if (!std::isfinite(gamma)) {
+      c->err = "non-finite gamma in SDSN";
+      return FRAM_ENUMERIC;
+    }
+  }
   stt->outer_iters = it;
   stt->sdsn_passes = total_passes;
   stt->sdsn_passes_last = last_passes;
@@ -480,6 +594,7 @@ void fram_default_options(fram_options* opt) {
   opt->sdsn_max = 1000;
   opt->tile = 0;
   opt->profile = 0;
+  opt->sdsn_mode = 0;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -501,6 +616,7 @@ void fram_destroy(fram_ctx* c) {
     if (c->hst) (void)hipHostFree(c->hst);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->flags) (void)hipFree(c->flags);
     if (c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -602,13 +718,40 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   DevState* st = at<DevState>(c, L.state);
   float* X = at<float>(c, L.X);
   HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
-  HIPCHK(fram::launch_tile_stats(L.bm, dK, ldk, X, n, L.np, partials(c, L, 0), st, s));
   int passes = 0;
   double gamma = 0.0;
   bool capped = false;
   fram_stats stt{};
-  r = run_sdsn_passes(c, L, n, X, st, lambda, o, 8, s, &passes, &gamma, &capped, &stt);
+  bool onchip = false;
+  r = use_onchip(c, L, o, &onchip);
   if (r != FRAM_OK) return r;
+  if (onchip) {
+    Prof prof{o.profile != 0, c, s, 0.0f};
+    r = timed(prof, &stt.ms_sdsn, nullptr, [&] {
+      fram_status q = run_sdsn_onchip(c, L, n, dK, ldk, X, nullptr, nullptr, Elem::F32, 0.95, st,
+                                      lambda, o, s);
+      return q == FRAM_OK ? hipSuccess : hipErrorUnknown;
+    });
+    if (r != FRAM_OK) return r;
+    r = read_state(c, st, s);
+    if (r != FRAM_OK) return r;
+    if (c->hst->invalid & 8) {
+      c->err = "on-chip SDSN barrier timed out";
+      return FRAM_EDEVICE;
+    }
+    passes = c->hst->passes;
+    gamma = c->hst->gamma;
+    capped = c->hst->capped != 0;
+    stt.sdsn_launches = passes;
+    if (!std::isfinite(gamma)) {
+      c->err = "non-finite gamma in SDSN";
+      return FRAM_ENUMERIC;
+    }
+  } else {
+    HIPCHK(fram::launch_tile_stats(L.bm, dK, ldk, X, n, L.np, partials(c, L, 0), st, s));
+    r = run_sdsn_passes(c, L, n, X, st, lambda, o, 8, s, &passes, &gamma, &capped, &stt);
+    if (r != FRAM_OK) return r;
+  }
   HIPCHK(fram::launch_copy_f32(X, L.np, dX, ldx, n, s));
   HIPCHK(hipStreamSynchronize(s));
   stt.sdsn_passes = passes;

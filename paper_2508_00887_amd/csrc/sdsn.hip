@@ -27,39 +27,10 @@
 // reduction), column partials stay in registers until the end of the tile;
 // both are summed in FP64 from per-lane FP32 sums of at most 16 elements.
 #include "fram_internal.h"
+#include "sdsn_common.h"
 
 namespace fram {
 namespace {
-
-template <int NT>
-__device__ double block_sum_f64(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] += sh[tid + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-template <int NT>
-__device__ float block_max_f32(float v, float* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] = fmaxf(sh[tid], sh[tid + s]);
-    __syncthreads();
-  }
-  const float r = sh[0];
-  __syncthreads();
-  return r;
-}
 
 struct TileArgs {
   const float* src;  // input matrix
@@ -88,7 +59,8 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int w = tid >> 6;
+  // Wave index as a scalar: row bounds then stay in SGPRs.
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int bn = blockIdx.x, bm = blockIdx.y, nb = gridDim.x;
   const int n = a.n, np = a.np;
   DevState* st = a.st;
@@ -103,7 +75,7 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     if (s_done) return;
     double part = 0.0;
     for (int t = tid; t < nb * nb; t += NT) part += a.in.tot[t];
-    const double S = block_sum_f64<NT>(part, s_red);
+    const double S = block_sum<NT>(part, s_red);
     if (a.k >= 2) {
       const double gamma_in = S / n - 1.0;
       if (gamma_in <= a.gamma_tol || a.k > a.max_passes) {
@@ -117,22 +89,24 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     } else {
       float m = -INFINITY;
       for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
-      m = block_max_f32<NT>(m, reinterpret_cast<float*>(s_red));
+      m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
       s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
     }
     const double sd = (double)s;
     const double dn = (double)n;
     const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
     for (int r = tid; r < BM; r += NT) {
-      const int i = bm * BM + r;
-      double ri = 0.0;
-      for (int b = 0; b < nb; ++b) ri += a.in.rowp[(size_t)b * np + i];
+      const double* rp = a.in.rowp + bm * BM + r;
+      auto ld = [&](int b) { return rp[(size_t)b * np]; };
+      const double ri = combine4(chain_sum(ld, nb, 0), chain_sum(ld, nb, 1),
+                                 chain_sum(ld, nb, 2), chain_sum(ld, nb, 3));
       s_a[r] = (float)(half - sd * ri / dn);
     }
     for (int c = tid; c < BM; c += NT) {
-      const int j = bn * BM + c;
-      double cj = 0.0;
-      for (int b = 0; b < nb; ++b) cj += a.in.colp[(size_t)b * np + j];
+      const double* cp = a.in.colp + bn * BM + c;
+      auto ld = [&](int b) { return cp[(size_t)b * np]; };
+      const double cj = combine4(chain_sum(ld, nb, 0), chain_sum(ld, nb, 1),
+                                 chain_sum(ld, nb, 2), chain_sum(ld, nb, 3));
       s_b[c] = (float)(half - sd * cj / dn);
     }
     __syncthreads();
@@ -214,9 +188,9 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     v += __shfl_xor(v, 2);
     if (p == 0) a.out.colp[(size_t)bm * np + bn * BM + c] = v;
   }
-  const double tt = block_sum_f64<NT>(rowsum, s_red);
+  const double tt = block_sum<NT>(rowsum, s_red);
   if (!PASS) {
-    const float tm = block_max_f32<NT>(lmax, reinterpret_cast<float*>(s_red));
+    const float tm = block_max<NT>(lmax, reinterpret_cast<float*>(s_red));
     if (tid == 0) a.out.tmax[bm * nb + bn] = tm;
   }
   if (tid == 0) a.out.tot[bm * nb + bn] = tt;

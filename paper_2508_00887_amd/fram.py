@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
         ("sdsn_max", ctypes.c_int),
         ("tile", ctypes.c_int),
         ("profile", ctypes.c_int),
+        ("sdsn_mode", ctypes.c_int),
     ]
 
 
@@ -167,10 +168,14 @@ def _check(ctx: int, st: int, where: str):
         raise FramError(st, where, f"{fram_status_str(st)}; {fram_last_error(ctx)}")
 
 
+SDSN_MODES = {"auto": 0, "stream": 1, "onchip": 2}
+
+
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
-             profile=False) -> Options:
+             profile=False, sdsn_mode="auto") -> Options:
     o = Options()
     o.profile = 1 if profile else 0
+    o.sdsn_mode = SDSN_MODES[sdsn_mode] if isinstance(sdsn_mode, str) else int(sdsn_mode)
     o.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     o.alpha = alpha
     o.gamma_tol = gamma_tol
@@ -231,22 +236,24 @@ class Context:
         _check(self.handle, st, "fram_solve_dev")
         return perm.astype(np.int64), obj.value, stats.as_dict()
 
-    def sdsn_project(self, K, theta=2.0, gamma_tol=1e-6, sdsn_max=1000, tile=0):
+    def sdsn_project(self, K, theta=2.0, gamma_tol=1e-6, sdsn_max=1000, tile=0,
+                     sdsn_mode="auto", profile=False):
         """fram_sdsn_project_ex on a host matrix; returns (X, stats dict)."""
         K = _f32(K)
         n = K.shape[0]
         X = np.empty((n, n), dtype=np.float32)
         stats = Stats()
-        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile)
+        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile, profile, sdsn_mode)
         st = self.lib.fram_sdsn_project_ex(self.handle, _ptr(K), n, theta, ctypes.byref(o),
                                            _ptr(X), ctypes.byref(stats))
         _check(self.handle, st, "fram_sdsn_project_ex")
         return X, stats.as_dict()
 
     def sdsn_project_dev(self, dK: int, ldk: int, n: int, dX: int, ldx: int, theta=2.0,
-                         gamma_tol=1e-6, sdsn_max=1000, tile=0, stream=0):
+                         gamma_tol=1e-6, sdsn_max=1000, tile=0, stream=0, sdsn_mode="auto",
+                         profile=False):
         stats = Stats()
-        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile)
+        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile, profile, sdsn_mode)
         st = self.lib.fram_sdsn_project_dev(self.handle, dK, ldk, n, theta, ctypes.byref(o), dX,
                                             ldx, ctypes.byref(stats), stream or None)
         _check(self.handle, st, "fram_sdsn_project_dev")

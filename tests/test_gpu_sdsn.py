@@ -65,9 +65,13 @@ def test_sdsn_matches_oracle(ctx, n, theta):
     X, st = ctx.sdsn_project(K, theta, gamma_tol=gth, sdsn_max=20000)
     k = st["sdsn_passes"]
     _, info = O.sdsn(K.astype(np.float64), theta, gth, 20000)
-    # gamma falls by ~1% per pass near gamma_tol at theta = 10, so FP32 rounding
-    # of gamma's trajectory may move the crossing by a few percent of the passes.
-    assert abs(k - info.passes) <= max(3, int(0.05 * info.passes)), (k, info.passes)
+    # Near gamma_tol gamma falls by ~1% per pass at theta = 10, and FP32
+    # rounding of the pass output slows that tail: an FP32 model of the same
+    # arithmetic in numpy needs the same ~10% more passes than FP64 (e.g. 1448
+    # vs 1308 at n = 1000), so the pass count is compared loosely and the
+    # matrices are compared exactly after the GPU's own pass count.
+    slack = 0.05 if theta <= 2.0 else 0.15
+    assert abs(k - info.passes) <= max(3, int(slack * info.passes)), (k, info.passes)
     D, _ = O.sdsn(K.astype(np.float64), theta, 0.0, max_passes=k)
     err = np.abs(X.astype(np.float64) - D).max()
     assert err <= k * 2e-6 / n + 1e-7, err
@@ -92,3 +96,24 @@ def test_sdsn_tile_variants_agree(ctx, tile):
     Xb, sb = ctx.sdsn_project(K, 2.0, tile=tile)
     assert abs(sa["sdsn_passes"] - sb["sdsn_passes"]) <= 1
     np.testing.assert_allclose(Xa, Xb, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [3, 65, 300, 1000, 2100, 4000])
+def test_onchip_equals_streaming_bitwise(ctx, n):
+    # Same formulas and the same fixed reduction order per tile: the on-chip
+    # projection (one cooperative launch) must reproduce the per-pass launches.
+    K = (np.random.default_rng(n).random((n, n)) ** 2).astype(np.float32)
+    Xs, ss = ctx.sdsn_project(K, 2.0, sdsn_mode="stream")
+    Xo, so = ctx.sdsn_project(K, 2.0, sdsn_mode="onchip")
+    assert ss["sdsn_passes"] == so["sdsn_passes"]
+    np.testing.assert_array_equal(Xs, Xo)
+
+
+@pytest.mark.parametrize("mode", ["stream", "onchip"])
+def test_modes_match_oracle_theta10(ctx, mode):
+    n = 500
+    K = (np.random.default_rng(42).random((n, n)) ** 2).astype(np.float32)
+    X, st = ctx.sdsn_project(K, 10.0, sdsn_max=20000, sdsn_mode=mode)
+    k = st["sdsn_passes"]
+    D, _ = O.sdsn(K.astype(np.float64), 10.0, 0.0, max_passes=k)
+    assert np.abs(X - D).max() <= k * 2e-6 / n + 1e-7

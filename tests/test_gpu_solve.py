@@ -162,3 +162,15 @@ def test_solve_many_equals_single_solves(ctx):
         p1, o1, _ = ctx.solve(pr.A, pr.B, iters=50, prec="bf16")
         np.testing.assert_array_equal(perm, p1)
         assert obj == o1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [50, 700, 2100])
+def test_onchip_and_streaming_solves_agree(ctx, n, prec):
+    pr = synth.make_pair(n, 0.3, 0.05, 5100 + n)
+    p1, o1, s1 = ctx.solve(pr.A, pr.B, iters=30, prec=prec, sdsn_mode="stream")
+    p2, o2, s2 = ctx.solve(pr.A, pr.B, iters=30, prec=prec, sdsn_mode="onchip")
+    np.testing.assert_array_equal(p1, p2)
+    assert o1 == o2
+    assert s1["sdsn_passes"] == s2["sdsn_passes"]
+    assert abs(s1["delta"] - s2["delta"]) <= 1e-12 * max(s1["delta"], 1e-300)
