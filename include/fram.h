@@ -96,6 +96,10 @@ typedef struct {
   int sdsn_max;          /* SDSN pass cap per call; default 1000                       */
   int tile;              /* 0 = automatic, else 64 / 128 / 256                          */
   int profile;           /* 1 = time kernels with HIP events into fram_stats (slower)  */
+  int stable_iters;      /* w > 0: also stop once the row argmax of N has been the same
+                            permutation for w consecutive iterations (a second stop
+                            rule beside delta <= tol, for precisions whose delta
+                            levels off above tol); 0 = off (default)                 */
   int sdsn_mode;         /* 0 = automatic, 1 = one streaming launch per SDSN pass,
                             2 = on-chip: all passes of a projection in one cooperative
                             launch with the iterate held in registers (FRAM_EINVAL if

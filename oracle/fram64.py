@@ -128,10 +128,16 @@ class FramInfo:
 
 def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
          iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6,
-         sdsn_max: int = 1000, N0: np.ndarray | None = None):
+         sdsn_max: int = 1000, N0: np.ndarray | None = None, stable_iters: int = 0):
     """Algorithm 1 up to (not including) the discretisation of step 10.
 
     Returns (N, FramInfo).  A and B are the *unscaled* inputs.
+
+    stable_iters = w > 0 adds a second stop (not in the paper, whose delta_th
+    is unspecified): stop once the row argmax of N (lowest column on ties)
+    has been the same permutation after w consecutive iterations; the loop
+    then stops at the first t where argmax(N^(t)) = argmax(N^(t-1)) = ... =
+    argmax(N^(t-w)).  A row argmax that is not a permutation never counts.
     """
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
@@ -141,6 +147,7 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
     passes, deltas, gammas = [], [], []
     converged, capped = False, False
     t = 0
+    prev_arg, same = None, 0
     while True:
         X = As @ N @ Bs                                       # step 5 (K absent)
         D, info = sdsn(X, theta, gamma_th, sdsn_max)           # step 6
@@ -157,6 +164,15 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
         if delta <= tol:
             converged = True
             break
+        if stable_iters > 0:
+            arg = np.argmax(N, axis=1)
+            is_perm = len(np.unique(arg)) == n
+            same = same + 1 if (is_perm and prev_arg is not None
+                                and np.array_equal(arg, prev_arg)) else 0
+            prev_arg = arg if is_perm else None
+            if same >= stable_iters:
+                converged = True
+                break
         if t >= iters:
             break
     return N, FramInfo(outer_iters=t, sdsn_passes=passes, deltas=deltas, gammas=gammas,
@@ -188,8 +204,9 @@ def accuracy(sigma: np.ndarray, perm: np.ndarray, inlier: np.ndarray | None = No
 
 
 def solve(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
-          iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6, sdsn_max: int = 1000):
+          iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6, sdsn_max: int = 1000,
+          stable_iters: int = 0):
     """Full FRAM: Algorithm 1 including step 10; returns (sigma, objective, N, FramInfo)."""
-    N, info = fram(A, B, theta, alpha, iters, tol, gamma_th, sdsn_max)
+    N, info = fram(A, B, theta, alpha, iters, tol, gamma_th, sdsn_max, stable_iters=stable_iters)
     sigma = discretize(N)
     return sigma, objective(A, B, sigma), N, info

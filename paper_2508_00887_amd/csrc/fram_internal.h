@@ -18,7 +18,8 @@ struct DevState {
   int total_passes;  // passes summed over projections (on-chip SDSN path)
   int max_passes;    // largest pass count of one projection (on-chip SDSN path)
   int capped;        // some projection hit the pass cap (on-chip SDSN path)
-  int pad0, pad1;
+  int arg_perm;      // row argmax of N is a permutation (argmax tracking)
+  int arg_same;      // ... and equals the previous iteration's argmax
   double gamma;      // gamma of the last SDSN output
   double delta;      // delta of the last outer update
   double dnum;       // ||N_new - N_old||_F^2 of the last update
@@ -100,6 +101,43 @@ hipError_t launch_sdsn_persistent(int bm, const PersistArgs& a, hipStream_t s);
 // st->delta from `nblocks` pairs of FP64 partial sums (num, den).
 hipError_t launch_delta_final(const double* part, int nblocks, DevState* st, hipStream_t s);
 
+// ---------------------------------------------------------------- batched
+// One pair of the batched solver.  Byte offsets are into the batch arena;
+// matrices are np x np (np = n rounded up to 32), zero padded.
+struct BatchPair {
+  int n, np;
+  long long a64, b64;         // FP64 unscaled inputs, n x n, leading dimension n
+  long long alp, blp, w, nlp; // GEMM-type A, B, W, N copies (np x np)
+  long long nf, x;            // FP32 N and X (np x np)
+  long long sigma;            // int32[n]
+  long long sigprev;          // int32[n], previous argmax (stability stop)
+};
+
+// Per-pair results of the batched solver.
+struct BatchResult {
+  double objective, delta, gamma;
+  int outer_iters, sdsn_passes, sdsn_passes_max, sdsn_passes_last;
+  int converged, sdsn_capped, is_perm, pad;
+};
+
+struct BatchArgs {
+  const BatchPair* pairs;
+  const int* order;     // processing order (largest n first)
+  int count;
+  int* next;            // work-queue counter, zero at launch
+  char* arena;
+  BatchResult* res;
+  double theta, alpha, gamma_tol, tol;
+  int iters, sdsn_max;
+  int stable_iters;     // argmax-stability stop (0 = off)
+  int objective_only;   // 1: only recompute objectives from sigma (after host assignment)
+};
+
+constexpr int kBatchMaxN = 512;  // largest pair the batched kernel takes
+
+// Persistent batched FRAM: `grid` workgroups pull pairs from the queue.
+hipError_t launch_fram_batch(Elem e, const BatchArgs& a, int grid, hipStream_t s);
+
 // N <- (1-alpha) N + alpha D with FP64 partial sums for delta; writes the
 // GEMM-operand copy Nlp in type e (skipped when e == F32 and Nlp == N).
 hipError_t launch_update(Elem e, const float* D, float* N, void* Nlp, int n, int np,
@@ -128,6 +166,13 @@ hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s);
 
 // sigma[i] = argmax_j N[i, j] (lowest j on ties), i < n.
 hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s);
+
+// Argmax tracking for the stability stop: cur (written by row_argmax) is
+// checked for being a permutation and compared with prev; then prev = cur.
+// Sets st->arg_perm and st->arg_same.  n <= kTrackMaxN.
+constexpr int kTrackMaxN = 16384;
+hipError_t launch_argmax_track(const int32_t* cur, int32_t* prev, int n, DevState* st,
+                               hipStream_t s);
 
 // st->objective = sum_{k,l} A_kl B_{sigma(k) sigma(l)} in FP64.
 hipError_t launch_objective(const double* A, const double* B, const int32_t* sigma, int n,

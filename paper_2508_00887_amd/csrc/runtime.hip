@@ -64,7 +64,7 @@ struct Layout {
   Elem e = Elem::F32;
   size_t A64 = 0, B64 = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
   size_t rowp[2] = {0, 0}, colp[2] = {0, 0}, tot[2] = {0, 0}, tmax[2] = {0, 0};
-  size_t upd = 0, mx = 0, obj = 0, sigma = 0, state = 0;
+  size_t upd = 0, mx = 0, obj = 0, sigma = 0, sigprev = 0, state = 0;
   int nupd = 1, nmax = 1, nobj = 1;
   size_t total = 0;
 };
@@ -111,6 +111,7 @@ Layout plan(int n, Elem e, int tile, Use use) {
   L.mx = take((size_t)L.nmax * 16);
   L.obj = take((size_t)L.nobj * 8);
   L.sigma = take((size_t)n * 4);
+  L.sigprev = take((size_t)n * 4);
   L.state = take(sizeof(DevState));
   L.total = off;
   return L;
@@ -126,6 +127,7 @@ fram_status check_options(const fram_options& o) {
   if (!(o.tile == 0 || o.tile == 64 || o.tile == 128 || o.tile == 256)) return FRAM_EINVAL;
   if (o.profile != 0 && o.profile != 1) return FRAM_EINVAL;
   if (o.sdsn_mode < 0 || o.sdsn_mode > 2) return FRAM_EINVAL;
+  if (o.stable_iters < 0) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -356,7 +358,6 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   a.alpha = (float)alpha;
   a.dpart = at<double>(c, L.upd);
   HIPCHK(fram::launch_sdsn_persistent(L.bm, a, s));
-  if (N != nullptr) HIPCHK(fram::launch_delta_final(a.dpart, L.nb * L.nb, st, s));
   return FRAM_OK;
 }
 
@@ -438,6 +439,8 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   bool any_capped = false, converged = false;
   double gamma = 0.0, delta = 0.0;
   int est = 8;
+  int stable = 0;
+  bool prev_perm = false;
   Prof prof{o.profile != 0, c, s, 0.0f};
   bool onchip = false;
   {
@@ -460,6 +463,10 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
         fram_status q = run_sdsn_onchip(c, L, n, X, L.np, nullptr, N, Nlp, e, o.alpha, st,
                                         theta, o, s);
         return q == FRAM_OK ? hipSuccess : hipErrorUnknown;
+      });
+      if (r != FRAM_OK) return r;
+      r = timed(prof, &stt->ms_update, nullptr, [&] {
+        return fram::launch_delta_final(at<double>(c, L.upd), L.nb * L.nb, st, s);
       });
       if (r != FRAM_OK) return r;
       if (prof.on) {
@@ -490,7 +497,12 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       });
       if (r != FRAM_OK) return r;
     }
-    if (tol > 0.0 || it == iters) {
+    const bool track = o.stable_iters > 0 && n <= fram::kTrackMaxN;
+    if (track) {
+      HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s));
+      HIPCHK(fram::launch_argmax_track(dsig, at<int32_t>(c, L.sigprev), n, st, s));
+    }
+    if (tol > 0.0 || track || it == iters) {
       r = read_state(c, st, s);
       if (r != FRAM_OK) return r;
       if (c->hst->invalid & 8) {
@@ -505,6 +517,17 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       if (delta <= tol) {
         converged = true;
         break;
+      }
+      if (track) {
+        // Same rule as the oracle: count consecutive iterations whose argmax is
+        // a permutation equal to the previous (also a permutation) one.
+        const bool is_perm = c->hst->arg_perm != 0;
+        stable = (is_perm && prev_perm && c->hst->arg_same) ? stable + 1 : 0;
+        prev_perm = is_perm;
+        if (stable >= o.stable_iters) {
+          converged = true;
+          break;
+        }
       }
     }
   }
@@ -595,6 +618,7 @@ void fram_default_options(fram_options* opt) {
   opt->tile = 0;
   opt->profile = 0;
   opt->sdsn_mode = 0;
+  opt->stable_iters = 0;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -833,12 +857,182 @@ fram_status fram_gradient(fram_ctx* c, const float* A, const float* N, const flo
   return FRAM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Batched solve of the pairs listed in `ids` (all 2 <= n <= kBatchMaxN) with
+// the persistent kernel; results go to perm_out / objective_out / stats.
+fram_status solve_batched(fram_ctx* c, const std::vector<int>& ids, const double* const* A,
+                          const double* const* B, const int* n, double theta, int iters,
+                          double tol, const fram_options& o, int32_t* const* perm_out,
+                          double* objective_out, fram_stats* stats) {
+  const Elem e = (Elem)o.prec;
+  const size_t es = fram::elem_size(e);
+  const int m = (int)ids.size();
+  std::vector<fram::BatchPair> pairs(m);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(bytes);
+    return (long long)at;
+  };
+  // Inputs first (contiguous, one upload), then the working matrices.
+  size_t in_elems = 0;
+  for (int q = 0; q < m; ++q) {
+    const int nn = n[ids[q]];
+    pairs[q].n = nn;
+    pairs[q].np = (nn + 31) / 32 * 32;
+    pairs[q].a64 = (long long)(in_elems * 8);
+    in_elems += (size_t)nn * nn;
+    pairs[q].b64 = (long long)(in_elems * 8);
+    in_elems += (size_t)nn * nn;
+  }
+  off = align_up(in_elems * 8);
+  size_t sig_elems = 0;
+  const size_t sig_base = off;
+  for (int q = 0; q < m; ++q) {
+    pairs[q].sigma = (long long)(sig_base + sig_elems * 4);
+    sig_elems += (size_t)pairs[q].n;
+  }
+  off = align_up(sig_base + sig_elems * 4);
+  for (int q = 0; q < m; ++q) pairs[q].sigprev = take((size_t)pairs[q].n * 4);
+  for (int q = 0; q < m; ++q) {
+    const size_t np2 = (size_t)pairs[q].np * pairs[q].np;
+    pairs[q].alp = take(np2 * es);
+    pairs[q].blp = take(np2 * es);
+    pairs[q].w = take(np2 * es);
+    pairs[q].nlp = (e == Elem::F32) ? 0 : take(np2 * es);
+    pairs[q].nf = take(np2 * 4);
+    pairs[q].x = take(np2 * 4);
+  }
+  const long long pairs_off = take(sizeof(fram::BatchPair) * m);
+  const long long order_off = take(sizeof(int) * m);
+  const long long next_off = take(sizeof(int));
+  const long long res_off = take(sizeof(fram::BatchResult) * m);
+  const size_t total = off;
+  if (c->budget != 0 && total > c->budget) {
+    c->err = "batched workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = c->stream;
+  char* ar = static_cast<char*>(c->ws);
+
+  // Largest pairs first (longest-processing-time order).
+  std::vector<int> order(m);
+  for (int q = 0; q < m; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return pairs[x].n > pairs[y].n; });
+  std::vector<double> staged(in_elems);
+  for (int q = 0; q < m; ++q) {
+    const size_t nn2 = (size_t)pairs[q].n * pairs[q].n;
+    std::memcpy(&staged[pairs[q].a64 / 8], A[ids[q]], nn2 * 8);
+    std::memcpy(&staged[pairs[q].b64 / 8], B[ids[q]], nn2 * 8);
+  }
+  HIPCHK(hipMemcpyAsync(ar, staged.data(), in_elems * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ar + pairs_off, pairs.data(), sizeof(fram::BatchPair) * m,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ar + order_off, order.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  HIPCHK(fram::launch_zero(ar + next_off, sizeof(int), s));
+
+  fram::BatchArgs a{};
+  a.pairs = reinterpret_cast<const fram::BatchPair*>(ar + pairs_off);
+  a.order = reinterpret_cast<const int*>(ar + order_off);
+  a.count = m;
+  a.next = reinterpret_cast<int*>(ar + next_off);
+  a.arena = ar;
+  a.res = reinterpret_cast<fram::BatchResult*>(ar + res_off);
+  a.theta = theta;
+  a.alpha = o.alpha;
+  a.gamma_tol = o.gamma_tol;
+  a.tol = tol;
+  a.iters = iters;
+  a.sdsn_max = o.sdsn_max;
+  a.stable_iters = o.stable_iters;
+  a.objective_only = 0;
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int grid = std::max(1, std::min(m, 3 * cus));
+  HIPCHK(fram::launch_fram_batch(e, a, grid, s));
+  std::vector<fram::BatchResult> res(m);
+  std::vector<int32_t> sig(sig_elems);
+  HIPCHK(hipMemcpyAsync(res.data(), ar + res_off, sizeof(fram::BatchResult) * m,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(sig.data(), ar + sig_base, sig_elems * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+
+  // Pairs whose row argmax collides: exact assignment on the host, then the
+  // objective of the new permutation on the device.
+  std::vector<int> fix;
+  for (int q = 0; q < m; ++q)
+    if (!res[q].is_perm) fix.push_back(q);
+  if (!fix.empty()) {
+    for (int q : fix) {
+      const int nn = pairs[q].n, np = pairs[q].np;
+      c->hostN.resize((size_t)nn * np);
+      HIPCHK(hipMemcpyAsync(c->hostN.data(), ar + pairs[q].nf, (size_t)nn * np * 4,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      int32_t* sq = &sig[(pairs[q].sigma - (long long)sig_base) / 4];
+      std::vector<int32_t> init(sq, sq + nn);
+      fram::host_lap_max(c->hostN.data(), nn, np, init.data(), sq);
+      HIPCHK(hipMemcpyAsync(ar + pairs[q].sigma, sq, (size_t)nn * 4, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipMemcpyAsync(ar + order_off, fix.data(), sizeof(int) * fix.size(),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(fram::launch_zero(ar + next_off, sizeof(int), s));
+    a.count = (int)fix.size();
+    a.objective_only = 1;
+    HIPCHK(fram::launch_fram_batch(e, a, std::max(1, std::min(a.count, 3 * cus)), s));
+    std::vector<fram::BatchResult> res2(m);
+    HIPCHK(hipMemcpyAsync(res2.data(), ar + res_off, sizeof(fram::BatchResult) * m,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int q : fix) res[q].objective = res2[q].objective;
+  }
+  for (int q = 0; q < m; ++q) {
+    const int p = ids[q];
+    const int32_t* sq = &sig[(pairs[q].sigma - (long long)sig_base) / 4];
+    std::memcpy(perm_out[p], sq, (size_t)pairs[q].n * 4);
+    objective_out[p] = res[q].objective;
+    if (!std::isfinite(res[q].objective) || !std::isfinite(res[q].delta) ||
+        !std::isfinite(res[q].gamma)) {
+      c->err = "non-finite value in batched pair " + std::to_string(p);
+      return FRAM_ENUMERIC;
+    }
+    if (stats) {
+      fram_stats& st = stats[p];
+      st = fram_stats{};
+      st.outer_iters = res[q].outer_iters;
+      st.sdsn_passes = res[q].sdsn_passes;
+      st.sdsn_passes_last = res[q].sdsn_passes_last;
+      st.sdsn_passes_max = res[q].sdsn_passes_max;
+      st.converged = res[q].converged;
+      st.sdsn_capped = res[q].sdsn_capped;
+      st.host_lap = res[q].is_perm ? 0 : 1;
+      st.gemm_tile = 32;
+      st.delta = res[q].delta;
+      st.gamma = res[q].gamma;
+    }
+  }
+  return FRAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
                                const double* const* B, const int* n, double lambda, int iters,
                                double tol, const fram_options* opt, int32_t* const* perm_out,
                                double* objective_out, fram_stats* stats) {
   if (!c || count < 1 || !A || !B || !n || !perm_out || !objective_out) return FRAM_EINVAL;
   fram_options o = opt ? *opt : defaults();
+  if (!opt) o.prec = FRAM_BF16;
   fram_status r = check_options(o);
   if (r != FRAM_OK) return r;
   for (int p = 0; p < count; ++p) {
@@ -851,14 +1045,36 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
       return r;
     }
   }
+  const double t0 = now_ms();
+  std::vector<int> batched, single;
   for (int p = 0; p < count; ++p) {
+    if (n[p] == 1) {
+      perm_out[p][0] = 0;
+      objective_out[p] = A[p][0] * B[p][0];
+      if (stats) stats[p] = fram_stats{};
+    } else if (n[p] <= fram::kBatchMaxN) {
+      batched.push_back(p);
+    } else {
+      single.push_back(p);
+    }
+  }
+  if (!batched.empty()) {
+    r = solve_batched(c, batched, A, B, n, lambda, iters, tol, o, perm_out, objective_out, stats);
+    if (r != FRAM_OK) return r;
+  }
+  // Pairs too large for one workgroup go through the single-pair path.
+  for (int p : single) {
     fram_stats st{};
     r = solve_host_impl(c, A[p], B[p], n[p], lambda, iters, tol, o, perm_out[p],
                         &objective_out[p], &st);
     if (stats) stats[p] = st;
-    c->last = st;
     if (r != FRAM_OK) return r;
   }
+  const double ms = now_ms() - t0;
+  if (stats)
+    for (int p = 0; p < count; ++p) stats[p].ms_total = ms;
+  c->last = stats ? stats[count - 1] : fram_stats{};
+  c->last.ms_total = ms;
   return FRAM_OK;
 }
 

@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
         ("sdsn_max", ctypes.c_int),
         ("tile", ctypes.c_int),
         ("profile", ctypes.c_int),
+        ("stable_iters", ctypes.c_int),
         ("sdsn_mode", ctypes.c_int),
     ]
 
@@ -172,8 +173,9 @@ SDSN_MODES = {"auto": 0, "stream": 1, "onchip": 2}
 
 
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
-             profile=False, sdsn_mode="auto") -> Options:
+             profile=False, sdsn_mode="auto", stable_iters=0) -> Options:
     o = Options()
+    o.stable_iters = int(stable_iters)
     o.profile = 1 if profile else 0
     o.sdsn_mode = SDSN_MODES[sdsn_mode] if isinstance(sdsn_mode, str) else int(sdsn_mode)
     o.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)

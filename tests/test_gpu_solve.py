@@ -154,14 +154,55 @@ def test_device_entry_point_rejects_invalid_device_input(ctx):
     torch.cuda.synchronize()
 
 
-def test_solve_many_equals_single_solves(ctx):
-    pairs = synth.batched_pairs(count=6)
-    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=50,
-                                        prec="bf16")
-    for pr, perm, obj in zip(pairs, perms, objs):
-        p1, o1, _ = ctx.solve(pr.A, pr.B, iters=50, prec="bf16")
-        np.testing.assert_array_equal(perm, p1)
-        assert obj == o1
+def _small_batch(count, seed, n_hi=160):
+    rng = np.random.default_rng(seed)
+    return [synth.make_pair(int(rng.integers(20, n_hi + 1)), float(rng.uniform(0.1, 0.5)), 0.03,
+                            seed * 1000 + i) for i in range(count)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_pairs_match_oracle(ctx, prec):
+    # The batched kernel (one workgroup per pair) against the FP64 oracle:
+    # FP32 GEMMs give the oracle's permutation, BF16 the accuracy gate.
+    pairs = _small_batch(8, 31)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=60,
+                                        prec=prec)
+    for pr, perm, obj, st in zip(pairs, perms, objs, stats):
+        s_or, obj_or, _, _ = O.solve(pr.A, pr.B, iters=60)
+        check_perm(perm, pr.n)
+        assert st["outer_iters"] == 60 and st["gemm_tile"] == 32
+        assert abs(obj - host_objective(pr.A, pr.B, perm)) <= 1e-12 * abs(obj)
+        if prec == "fp32":
+            np.testing.assert_array_equal(perm, s_or)
+            assert abs(obj - obj_or) <= 1e-5 * abs(obj_or)
+        else:
+            assert abs(obj - obj_or) <= 1e-3 * abs(obj_or)
+            assert O.accuracy(perm, pr.perm) >= O.accuracy(s_or, pr.perm) - 0.005
+
+
+def test_batched_result_is_the_same_alone_and_in_the_mix(ctx):
+    pairs = _small_batch(40, 32, n_hi=300)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=40)
+    for q in (0, 7, 39):
+        p1, o1, s1 = ctx.solve_many([pairs[q].A], [pairs[q].B], iters=40)
+        np.testing.assert_array_equal(p1[0], perms[q])
+        assert o1[0] == objs[q]
+        assert s1[0]["sdsn_passes"] == stats[q]["sdsn_passes"]
+
+
+def test_batched_mixed_sizes_and_tolerance(ctx):
+    # n = 1 is answered on the host, n > 512 goes through the single-pair path.
+    big = synth.make_pair(600, 0.3, 0.05, 6060)
+    one = np.zeros((1, 1))
+    small = synth.make_pair(40, 0.4, 0.02, 6061)
+    perms, objs, stats = ctx.solve_many([one, small.A, big.A], [one, small.B, big.B], iters=100,
+                                        tol=1e-4, prec="bf16")
+    assert list(perms[0]) == [0] and objs[0] == 0.0
+    for pr, perm, obj, st in zip([small, big], perms[1:], objs[1:], stats[1:]):
+        check_perm(perm, pr.n)
+        assert abs(obj - host_objective(pr.A, pr.B, perm)) <= 1e-12 * abs(obj)
+        assert st["converged"] == 1 and st["delta"] <= 1e-4
+    assert stats[2]["gemm_tile"] != 32
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -174,3 +215,32 @@ def test_onchip_and_streaming_solves_agree(ctx, n, prec):
     assert o1 == o2
     assert s1["sdsn_passes"] == s2["sdsn_passes"]
     assert abs(s1["delta"] - s2["delta"]) <= 1e-12 * max(s1["delta"], 1e-300)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_stability_stop_matches_oracle(ctx, seed):
+    pr = next(synth.config_pairs(0, [seed]))
+    s_or, obj_or, _, info = O.solve(pr.A, pr.B, iters=100, stable_iters=3)
+    perm, obj, st = ctx.solve(pr.A, pr.B, iters=100, prec="fp32", stable_iters=3)
+    np.testing.assert_array_equal(perm, s_or)
+    assert abs(obj - obj_or) <= 1e-5 * abs(obj_or)
+    assert abs(st["outer_iters"] - info.outer_iters) <= 2
+    pb, ob, sb = ctx.solve_many([pr.A], [pr.B], iters=100, prec="fp32", stable_iters=3)
+    np.testing.assert_array_equal(pb[0], s_or)
+    assert abs(sb[0]["outer_iters"] - info.outer_iters) <= 2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
+def test_n4000_stability_stop_accuracy_gate(ctx, prec):
+    # The n = 4000 workload with delta <= 1e-6 or a 3-iteration stable argmax:
+    # the low-precision paths level off above delta = 1e-6, the second rule
+    # stops them; the result must meet the accuracy gate against the oracle's
+    # delta-converged solve.
+    g = _golden("fram_c2_seed2000.json")
+    pr = next(synth.config_pairs(2, [0]))
+    perm, obj, st = ctx.solve(pr.A, pr.B, theta=2.0, iters=100, tol=1e-6, prec=prec,
+                              stable_iters=3)
+    check_perm(perm, pr.n)
+    assert st["outer_iters"] < 100
+    assert abs(obj - g["objective"]) <= 1e-3 * abs(g["objective"])
+    assert O.accuracy(perm, pr.perm, pr.inlier) >= g["accuracy"] - 0.005

@@ -183,3 +183,24 @@ def test_accuracy_counts_inliers_only():
     sigma = np.array([2, 0, 3, 3])
     assert O.accuracy(sigma, perm) == 0.75
     assert O.accuracy(sigma, perm, np.array([True, True, False, True])) == 1.0
+
+
+def test_stable_argmax_stop():
+    # The optional argmax-stability stop: the loop ends at the first t whose
+    # row argmax equals those of the w previous iterates (all permutations).
+    pr = next(synth.config_pairs(0, [0]))  # n = 50 workload, seed 0
+    _, full = O.fram(pr.A, pr.B, iters=60)
+    As, Bs, _ = O.prescale(pr.A, pr.B)
+    # Recompute the iterates to find the first stable run of length 3.
+    N = np.zeros((50, 50))
+    args = []
+    for t in range(60):
+        D, _ = O.sdsn(As @ N @ Bs, 2.0, 1e-6, 1000)
+        N = 0.05 * N + 0.95 * D
+        a = np.argmax(N, axis=1)
+        args.append(a if len(np.unique(a)) == 50 else None)
+    t_stop = next(t for t in range(3, 60) if all(args[t - d] is not None for d in range(4))
+                  and all(np.array_equal(args[t], args[t - d]) for d in range(1, 4))) + 1
+    _, info = O.fram(pr.A, pr.B, iters=60, stable_iters=3)
+    assert info.outer_iters == t_stop and info.converged
+    assert info.deltas == full.deltas[:t_stop]
