@@ -1,0 +1,215 @@
+"""Continuous-batching request loop for FRAM solves on one GPU.
+
+Requests (graph pairs) arrive over time.  Each is admitted when its device
+workspace fits the HBM budget that is still free, and is solved on one of a
+few worker contexts, each with its own HIP stream and workspace, so the
+kernels of different requests overlap on the device:
+
+* requests with n <= ``small_n`` are gathered by the batching worker, which
+  takes every small request waiting when it becomes free and solves them in
+  one launch of the batched kernel (fram_solve_many) -- one workgroup per
+  request, so a request's result is the same whether it ran alone or with
+  others;
+* larger requests go to the single-pair workers (fram_solve_ex) with
+  per-pass SDSN launches, which share the device with whatever else runs.
+
+Latency is measured from a request's arrival to the moment its result is
+back on the host.  The loop is plain Python around native calls (ctypes
+releases the GIL during each call, so the workers run concurrently).
+"""
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+from collections import deque
+
+import numpy as np
+
+from .fram import Context, fram_workspace_bytes, PRECISIONS
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    A: np.ndarray
+    B: np.ndarray
+    arrival: float            # seconds since the trace start
+    done: float = -1.0        # completion time, same clock
+    perm: np.ndarray | None = None
+    objective: float = float("nan")
+    stats: dict | None = None
+    worker: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def latency_ms(self) -> float:
+        return 1e3 * (self.done - self.arrival)
+
+
+class Budget:
+    """HBM admission: a counting semaphore over bytes."""
+
+    def __init__(self, total: int):
+        self.total = int(total)
+        self.free = int(total)
+        self.cv = threading.Condition()
+
+    def acquire(self, nbytes: int, stop: threading.Event) -> bool:
+        nbytes = min(int(nbytes), self.total)
+        with self.cv:
+            while self.free < nbytes and not stop.is_set():
+                self.cv.wait(0.01)
+            if stop.is_set():
+                return False
+            self.free -= nbytes
+            return True
+
+    def release(self, nbytes: int):
+        nbytes = min(int(nbytes), self.total)
+        with self.cv:
+            self.free += nbytes
+            self.cv.notify_all()
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 3,
+                 small_n: int = 512, max_batch: int = 256, prec: str = "bf16",
+                 theta: float = 2.0, iters: int = 100, tol: float = 1e-6,
+                 stable_iters: int = 3, device: int = 0, context_factory=None):
+        self.small_n = small_n
+        self.max_batch = max_batch
+        self.opts = dict(prec=prec, stable_iters=stable_iters)
+        self.theta, self.iters, self.tol = theta, iters, tol
+        self.budget = Budget(hbm_budget_bytes)
+        self.q_small: deque[Request] = deque()
+        self.q_large: deque[Request] = deque()
+        self.cv = threading.Condition()
+        self.stop = threading.Event()
+        self.completed: list[Request] = []
+        self.t0 = 0.0
+        make = context_factory or Context
+        self.ctx_small = make(device)
+        self.ctx_large = [make(device) for _ in range(large_workers)]
+        self.threads = [threading.Thread(target=self._small_loop, daemon=True)]
+        self.threads += [threading.Thread(target=self._large_loop, args=(c, f"large{i}"),
+                                          daemon=True) for i, c in enumerate(self.ctx_large)]
+
+    # ------------------------------------------------------------- clock
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # ------------------------------------------------------------- bytes
+    def _bytes(self, n: int, batched: bool) -> int:
+        p = PRECISIONS[self.opts["prec"]]
+        np_ = (n + 31) // 32 * 32
+        es = 4 if p == 0 else 2
+        if batched:
+            return 16 * n * n + np_ * np_ * (4 * es + 8) + 8 * n + 4096
+        try:
+            return fram_workspace_bytes(n, p)
+        except (ImportError, OSError):
+            return 16 * n * n + 4 * np_ * np_ * (3 * es + 12)
+
+    # ------------------------------------------------------------- API
+    def start(self):
+        self.t0 = time.perf_counter()
+        for t in self.threads:
+            t.start()
+
+    def submit(self, req: Request):
+        with self.cv:
+            (self.q_small if req.n <= self.small_n else self.q_large).append(req)
+            self.cv.notify_all()
+
+    def shutdown(self):
+        self.stop.set()
+        with self.cv:
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join()
+        for c in [self.ctx_small, *self.ctx_large]:
+            c.close()
+
+    # ------------------------------------------------------------- workers
+    def _finish(self, req: Request, perm, obj, st, worker: str):
+        req.perm, req.objective, req.stats, req.worker = perm, obj, st, worker
+        req.done = self.now()
+        with self.cv:
+            self.completed.append(req)
+            self.cv.notify_all()
+
+    def _small_loop(self):
+        while True:
+            with self.cv:
+                while not self.q_small and not self.stop.is_set():
+                    self.cv.wait(0.01)
+                if self.stop.is_set() and not self.q_small:
+                    return
+                batch = []
+                while self.q_small and len(batch) < self.max_batch:
+                    batch.append(self.q_small.popleft())
+            nbytes = sum(self._bytes(r.n, True) for r in batch)
+            if not self.budget.acquire(nbytes, self.stop):
+                return
+            try:
+                perms, objs, stats = self.ctx_small.solve_many(
+                    [r.A for r in batch], [r.B for r in batch], theta=self.theta,
+                    iters=self.iters, tol=self.tol, **self.opts)
+            finally:
+                self.budget.release(nbytes)
+            for r, p, o, s in zip(batch, perms, objs, stats):
+                self._finish(r, p, o, s, "batched")
+
+    def _large_loop(self, ctx: Context, name: str):
+        while True:
+            with self.cv:
+                while not self.q_large and not self.stop.is_set():
+                    self.cv.wait(0.01)
+                if self.stop.is_set() and not self.q_large:
+                    return
+                req = self.q_large.popleft()
+            nbytes = self._bytes(req.n, False)
+            if not self.budget.acquire(nbytes, self.stop):
+                return
+            try:
+                perm, obj, st = ctx.solve(req.A, req.B, theta=self.theta, iters=self.iters,
+                                          tol=self.tol, sdsn_mode="stream", **self.opts)
+            finally:
+                self.budget.release(nbytes)
+            self._finish(req, perm, obj, st, name)
+
+    # ------------------------------------------------------------- trace replay
+    def replay(self, requests: list[Request], timeout_s: float = 600.0) -> list[Request]:
+        """Submit each request at its arrival time; wait for all results."""
+        self.start()
+        for r in sorted(requests, key=lambda r: r.arrival):
+            delay = r.arrival - self.now()
+            if delay > 0:
+                time.sleep(delay)
+            self.submit(r)
+        deadline = time.perf_counter() + timeout_s
+        with self.cv:
+            while len(self.completed) < len(requests) and time.perf_counter() < deadline:
+                self.cv.wait(0.05)
+        self.shutdown()
+        return list(self.completed)
+
+
+def summarize(done: list[Request], warmup_s: float, duration_s: float) -> dict:
+    """p50 / p99 latency and throughput over requests arriving after warm-up."""
+    meas = [r for r in done if r.arrival >= warmup_s and r.done >= 0]
+    lat = np.array([r.latency_ms for r in meas]) if meas else np.array([np.nan])
+    last = max((r.done for r in meas), default=warmup_s)
+    return dict(
+        requests=len(meas),
+        p50_ms=float(np.percentile(lat, 50)),
+        p99_ms=float(np.percentile(lat, 99)),
+        mean_ms=float(np.mean(lat)),
+        solves_per_s=len(meas) / max(1e-9, last - warmup_s),
+        offered_per_s=len(meas) / duration_s,
+        batched=sum(1 for r in meas if r.worker == "batched"),
+    )

@@ -1,0 +1,129 @@
+"""Serving loop: admission, batching and overlap logic on the CPU with a fake
+executor; on the GPU, every result must equal the same request solved alone."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2508_00887_amd.serve import Budget, Request, Server, summarize
+
+
+class FakeContext:
+    """Deterministic stand-in for a libfram context: the 'solution' is a
+    function of the inputs only, and solving takes time proportional to n^2."""
+    live = 0
+    peak = 0
+    lock = threading.Lock()
+
+    def __init__(self, device=0):
+        self.calls = []
+
+    @staticmethod
+    def _answer(A):
+        n = A.shape[0]
+        return np.argsort(-A.sum(1), kind="stable"), float(A.sum())
+
+    def _work(self, n2):
+        with FakeContext.lock:
+            FakeContext.live += 1
+            FakeContext.peak = max(FakeContext.peak, FakeContext.live)
+        time.sleep(1e-7 * n2)
+        with FakeContext.lock:
+            FakeContext.live -= 1
+
+    def solve(self, A, B, **kw):
+        self.calls.append(("solve", A.shape[0], kw))
+        self._work(A.shape[0] ** 2)
+        p, o = self._answer(A)
+        return p, o, {"outer_iters": 1}
+
+    def solve_many(self, As, Bs, **kw):
+        self.calls.append(("many", [a.shape[0] for a in As], kw))
+        self._work(sum(a.shape[0] ** 2 for a in As))
+        out = [self._answer(a) for a in As]
+        return [p for p, _ in out], np.array([o for _, o in out]), [{"outer_iters": 1}] * len(As)
+
+    def close(self):
+        pass
+
+
+def _trace(count, rate, seed, n_lo=30, n_hi=900):
+    rng = np.random.default_rng(seed)
+    t, reqs = 0.0, []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        A = rng.random((n, n))
+        reqs.append(Request(rid=i, A=A + A.T, B=A + A.T, arrival=t))
+    return reqs
+
+
+def test_budget_blocks_until_released():
+    b = Budget(100)
+    stop = threading.Event()
+    assert b.acquire(70, stop)
+    got = []
+    th = threading.Thread(target=lambda: got.append(b.acquire(50, stop)))
+    th.start()
+    time.sleep(0.05)
+    assert not got  # 70 + 50 > 100: waits
+    b.release(70)
+    th.join(1.0)
+    assert got == [True] and b.free == 50
+
+
+def test_server_routes_batches_and_completes_everything():
+    FakeContext.peak = 0
+    reqs = _trace(120, 400.0, 1)
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=2, small_n=256, context_factory=FakeContext)
+    done = srv.replay(reqs, timeout_s=60)
+    assert len(done) == len(reqs)
+    for r in done:
+        p, o = FakeContext._answer(r.A)
+        np.testing.assert_array_equal(r.perm, p)
+        assert r.objective == o and r.done >= r.arrival
+        assert (r.worker == "batched") == (r.n <= 256)
+    many = [c for c in srv.ctx_small.calls if c[0] == "many"]
+    assert any(len(c[1]) > 1 for c in many), "small requests waiting together share a launch"
+    assert FakeContext.peak >= 2, "requests overlap across workers"
+    s = summarize(done, warmup_s=0.0, duration_s=reqs[-1].arrival)
+    assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_admission_respects_budget():
+    # A budget that fits one large workspace at a time serialises large requests.
+    reqs = [Request(rid=i, A=np.ones((600, 600)), B=np.ones((600, 600)), arrival=0.0)
+            for i in range(4)]
+    FakeContext.peak = 0
+    srv = Server(hbm_budget_bytes=1, large_workers=3, small_n=256, context_factory=FakeContext)
+    done = srv.replay(reqs, timeout_s=60)
+    assert len(done) == 4 and FakeContext.peak == 1
+
+
+@pytest.mark.gpu
+def test_served_results_equal_solving_alone():
+    from paper_2508_00887_amd import Context
+    rng = np.random.default_rng(4000)
+    reqs = []
+    t = 0.0
+    for i in range(24):
+        t += rng.exponential(1.0 / 60.0)
+        n = int(round(np.exp(rng.uniform(np.log(30), np.log(900)))))
+        pr = synth.make_pair(n, 0.3, 0.05, 4000 * 1000 + i)
+        reqs.append(Request(rid=i, A=pr.A, B=pr.B, arrival=t))
+    srv = Server(hbm_budget_bytes=16 << 30, large_workers=3, small_n=512)
+    done = srv.replay(reqs, timeout_s=300)
+    assert len(done) == len(reqs)
+    with Context(0) as ctx:
+        for r in done:
+            if r.worker == "batched":
+                p, o, _ = ctx.solve_many([r.A], [r.B], iters=100, tol=1e-6, prec="bf16",
+                                         stable_iters=3)
+                p, o = p[0], o[0]
+            else:
+                p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stable_iters=3,
+                                    sdsn_mode="stream")
+            np.testing.assert_array_equal(r.perm, p)
+            assert r.objective == o
