@@ -24,6 +24,8 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+// 16-byte fragment as a native vector: arrays of these are kept in VGPRs.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 template <Elem E>
 struct Mfma;
@@ -31,7 +33,7 @@ struct Mfma;
 template <>
 struct Mfma<Elem::BF16> {
   static constexpr int kPerChunk = 8;
-  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+  __device__ static inline void mac(const v4u& a, const v4u& b, f32x16& c) {
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
@@ -43,7 +45,7 @@ struct Mfma<Elem::BF16> {
 template <>
 struct Mfma<Elem::F16> {
   static constexpr int kPerChunk = 8;
-  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+  __device__ static inline void mac(const v4u& a, const v4u& b, f32x16& c) {
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
                                                 __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
   }
@@ -57,7 +59,7 @@ struct Mfma<Elem::F32> {
   static constexpr int kPerChunk = 4;
   // Lane l holds A[row l%32][k-slot l/32] per instruction; the four floats of
   // the chunk are four k-slots, applied identically to the A and B fragments.
-  __device__ static inline void mac(const uint4& a, const uint4& b, f32x16& c) {
+  __device__ static inline void mac(const v4u& a, const v4u& b, f32x16& c) {
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
@@ -73,14 +75,14 @@ constexpr int kChunks = 8;  // 16-byte chunks per LDS row (128 bytes of K)
 __device__ __forceinline__ int swz(int row, int ch) { return ch ^ (row & 7); }
 
 template <Elem E, int BM, bool OUT_F32>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const uint4* __restrict__ P,
-                                                      const uint4* __restrict__ Q,
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
+                                                      const v4u* __restrict__ Q,
                                                       void* __restrict__ C, int np, int ld,
                                                       int ktiles) {
   constexpr int WT = BM / 2;          // wave tile edge
   constexpr int F = WT / 32;          // MFMA blocks per wave tile edge
   constexpr int LOADS = BM * kChunks / 256;
-  __shared__ uint4 smem[2][2][BM][kChunks];
+  __shared__ v4u smem[2][2][BM][kChunks];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -104,50 +106,74 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const uint4* __restrict__ 
 
   const int lrow = tid >> 3;  // 0..31
   const int lch = tid & 7;
-  uint4 ra[LOADS], rb[LOADS];
-
-  auto gload = [&](int kt) {
-#pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const size_t r = (size_t)(lrow + 32 * i);
-      ra[i] = P[(m0 + r) * ldc + kt * kChunks + lch];
-      rb[i] = Q[(n0 + r) * ldc + kt * kChunks + lch];
-    }
-  };
-  auto sstore = [&](int st) {
-#pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const int r = lrow + 32 * i;
-      smem[st][0][r][swz(r, lch)] = ra[i];
-      smem[st][1][r][swz(r, lch)] = rb[i];
-    }
-  };
-
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int half = lane >> 5;
   const int l32 = lane & 31;
+  const v4u* pg = P + (size_t)(m0 + lrow) * ldc + lch;
+  const v4u* qg = Q + (size_t)(n0 + lrow) * ldc + lch;
+  const size_t rstep = (size_t)32 * ldc;  // 32 rows further down
+
+  // Prefetch registers for the next K tile.  No lambdas here: an array that a
+  // lambda captures by reference is kept in scratch memory.
+  v4u ra[LOADS], rb[LOADS];
+#pragma unroll
+  for (int i = 0; i < LOADS; ++i) {
+    ra[i] = pg[i * rstep];
+    rb[i] = qg[i * rstep];
+  }
+#pragma unroll
+  for (int i = 0; i < LOADS; ++i) {
+    const int r = lrow + 32 * i;
+    smem[0][0][r][swz(r, lch)] = ra[i];
+    smem[0][1][r][swz(r, lch)] = rb[i];
+  }
+  __syncthreads();
+
   for (int kt = 0; kt < ktiles; ++kt) {
     const int st = kt & 1;
-    if (kt + 1 < ktiles) gload(kt + 1);
+    const bool more = kt + 1 < ktiles;
+    if (more) {
+      const size_t ko = (size_t)(kt + 1) * kChunks;
+#pragma unroll
+      for (int i = 0; i < LOADS; ++i) {
+        ra[i] = pg[i * rstep + ko];
+        rb[i] = qg[i * rstep + ko];
+      }
+    }
+    // Fragments of step s + 1 are read from LDS while step s runs on MFMA.
+    v4u a[2][F], b[2][F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const int ra_ = wm * WT + f * 32 + l32;
+      const int rb_ = wn * WT + f * 32 + l32;
+      a[0][f] = smem[st][0][ra_][swz(ra_, half)];
+      b[0][f] = smem[st][1][rb_][swz(rb_, half)];
+    }
 #pragma unroll
     for (int s = 0; s < kChunks / 2; ++s) {
-      const int ch = 2 * s + half;
-      uint4 a[F], b[F];
+      const int cur = s & 1;
+      if (s + 1 < kChunks / 2) {
+        const int ch = 2 * (s + 1) + half;
 #pragma unroll
-      for (int f = 0; f < F; ++f) {
-        const int ra_ = wm * WT + f * 32 + l32;
-        const int rb_ = wn * WT + f * 32 + l32;
-        a[f] = smem[st][0][ra_][swz(ra_, ch)];
-        b[f] = smem[st][1][rb_][swz(rb_, ch)];
+        for (int f = 0; f < F; ++f) {
+          const int ra_ = wm * WT + f * 32 + l32;
+          const int rb_ = wn * WT + f * 32 + l32;
+          a[cur ^ 1][f] = smem[st][0][ra_][swz(ra_, ch)];
+          b[cur ^ 1][f] = smem[st][1][rb_][swz(rb_, ch)];
+        }
       }
 #pragma unroll
       for (int i = 0; i < F; ++i)
 #pragma unroll
-        for (int j = 0; j < F; ++j) Mfma<E>::mac(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < F; ++j) Mfma<E>::mac(a[cur][i], b[cur][j], acc[i][j]);
     }
-    if (kt + 1 < ktiles) sstore(st ^ 1);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < LOADS; ++i) {
+        const int r = lrow + 32 * i;
+        smem[st ^ 1][0][r][swz(r, lch)] = ra[i];
+        smem[st ^ 1][1][r][swz(r, lch)] = rb[i];
+      }
+    }
     __syncthreads();
   }
 
@@ -178,8 +204,8 @@ hipError_t launch_e(int bm, const void* P, const void* Q, void* C, int n, int np
   const int ktiles = (n + kelems - 1) / kelems;
   const int nb = np / bm;
   dim3 grid(nb * nb), block(256);
-  const uint4* p = static_cast<const uint4*>(P);
-  const uint4* q = static_cast<const uint4*>(Q);
+  const v4u* p = static_cast<const v4u*>(P);
+  const v4u* q = static_cast<const v4u*>(Q);
   switch (bm) {
     case 64:
       gemm_nt_kernel<E, 64, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);

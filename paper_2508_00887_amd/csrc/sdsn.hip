@@ -23,9 +23,9 @@
 //
 // Tiles are BM x BM with 4*BM threads: each wave streams 16 rows of the tile,
 // each lane a float4 of columns, so every global access of a wave is one or
-// more contiguous 1 KB runs.  Row partials go through LDS (a transposing
-// reduction), column partials stay in registers until the end of the tile;
-// both are summed in FP64 from per-lane FP32 sums of at most 16 elements.
+// more contiguous 1 KB runs.  Row partials are summed in FP64 across the lanes
+// of a row with DPP lane exchanges; column partials stay in registers until
+// the end of the tile and are then summed in FP64 through LDS.
 #include "fram_internal.h"
 #include "sdsn_common.h"
 
@@ -47,11 +47,11 @@ struct TileArgs {
 // PASS = true : one SDSN pass, in place on dst (== src, ld np).
 template <int BM, bool PASS>
 __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
-  constexpr int NT = 4 * BM;
-  constexpr int LPR = BM / 4;       // lanes per tile row
-  constexpr int RPW = 64 / LPR;     // tile rows per wave step
-  constexpr int STEPS = 16 / RPW;   // each wave covers 16 rows
-  __shared__ float s_rowred[BM][LPR + 1];
+  constexpr int NT = TileShape<BM>::NT;
+  constexpr int LPR = TileShape<BM>::LPR;      // lanes per tile row
+  constexpr int RPW = TileShape<BM>::RPW;      // tile rows per wave step
+  constexpr int STEPS = TileShape<BM>::STEPS;  // each wave covers 16 rows
+  __shared__ double s_rowsum[BM];
   __shared__ float s_colred[16][BM];
   __shared__ float s_a[BM];
   __shared__ float s_b[BM];
@@ -158,42 +158,14 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     } else if (!PASS && a.dst != nullptr && a.dst != a.src) {
       *reinterpret_cast<float4*>(a.dst + (size_t)i * np + j) = y;
     }
-    const float rs = (y.x + y.y) + (y.z + y.w);
-    s_rowred[rl][lc] = rs;
-    cacc.x += y.x;
-    cacc.y += y.y;
-    cacc.z += y.z;
-    cacc.w += y.w;
+    tile_step_sums<BM>(y, rl, s_rowsum, cacc);
   }
-  *reinterpret_cast<float4*>(&s_colred[w * RPW + q][cl]) = cacc;
-  __syncthreads();
-
-  double rowsum;
-  {  // row partials: 4 threads per row, fixed order, FP64
-    const int r = tid >> 2, p = tid & 3;
-    double v = 0.0;
-#pragma unroll
-    for (int u = 0; u < LPR / 4; ++u) v += (double)s_rowred[r][p * (LPR / 4) + u];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (p == 0) a.out.rowp[(size_t)bn * np + bm * BM + r] = v;
-    rowsum = (p == 0) ? v : 0.0;
-  }
-  {  // column partials, FP64
-    const int c = tid >> 2, p = tid & 3;
-    double v = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v += (double)s_colred[p * 4 + u][c];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (p == 0) a.out.colp[(size_t)bm * np + bn * BM + c] = v;
-  }
-  const double tt = block_sum<NT>(rowsum, s_red);
+  tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.out.rowp, a.out.colp, a.out.tot, bm, bn,
+                    nb, np);
   if (!PASS) {
     const float tm = block_max<NT>(lmax, reinterpret_cast<float*>(s_red));
     if (tid == 0) a.out.tmax[bm * nb + bn] = tm;
   }
-  if (tid == 0) a.out.tot[bm * nb + bn] = tt;
 }
 
 template <bool PASS>

@@ -16,136 +16,75 @@
 // in registers it updates N <- (1-alpha) N + alpha D, writes the GEMM-type
 // copy of N and FP64 partial sums for delta, so X is never written back.
 //
-// The pass arithmetic is the one of sdsn.hip: Y = max(0, fma(s, x, alpha_i +
-// beta_j)) with the symmetric FP64 split of the P1 correction (eq. P1_sol).
+// The pass arithmetic and every reduction are those of sdsn.hip (shared in
+// sdsn_common.h), so both kernels give bit-identical iterates:
+// Y = max(0, fma(s, x, alpha_i + beta_j)) with the symmetric FP64 split of the
+// P1 correction (eq. P1_sol).
 #include "fram_internal.h"
 #include "sdsn_common.h"
 
 namespace fram {
 namespace {
 
-// Grid-wide barrier without a contended counter.  Every wave first waits for
-// its own outstanding global stores; thread 0 then makes the workgroup's
-// stores visible device-wide (one agent-scope release fence) and publishes
-// the barrier's epoch in the workgroup's own flag.  Workgroup 0 waits for all
-// flags and publishes the epoch in a release flag that every workgroup waits
-// for.  Polling uses relaxed loads; one agent-scope acquire fence follows a
-// successful wait.  Epochs grow monotonically across launches (the host passes
-// a fresh 2^24-aligned base per launch), so flags never need resetting.
-// Waits are bounded: a workgroup that gives up returns false and the caller
-// leaves the pass loop, so the grid always drains.
-__device__ bool grid_barrier(unsigned long long* flags, unsigned long long epoch, int spin_limit) {
-  __shared__ int s_ok;
-  const int G = gridDim.x;
-  unsigned long long* release = flags + G;
+// Grid-wide barrier, arrival half: every wave waits for its own global
+// stores, then thread 0 makes the workgroup's stores visible device-wide (one
+// agent-scope release fence) and publishes the epoch in the workgroup's flag.
+__device__ __forceinline__ void barrier_arrive(unsigned long long* flags,
+                                               unsigned long long epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_ok = 1;
   }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int t = threadIdx.x; t < G; t += blockDim.x) {
-      int spins = 0;
-      while (__hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > spin_limit) {
-          s_ok = 0;
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_ok) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      __hip_atomic_store(release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  if (threadIdx.x == 0 && s_ok) {
+}
+
+// Waiting half: every workgroup polls all flags itself (thread t watches
+// flag t, relaxed loads), so the barrier costs one cross-chip round trip
+// after the last arrival.  Epochs grow monotonically across launches (the
+// host passes a fresh 2^24-aligned base per launch), so flags never need
+// resetting and a flag already past `epoch` also counts.  Waits are bounded:
+// a workgroup that gives up returns false and its caller leaves the pass loop,
+// so the grid always drains.  One agent-scope acquire fence follows.
+__device__ __forceinline__ bool barrier_wait(unsigned long long* flags, unsigned long long epoch,
+                                             int spin_limit, int* s_ok) {
+  const int G = gridDim.x;
+  int ok = 1;
+  for (int t = threadIdx.x; t < G; t += blockDim.x) {
     int spins = 0;
-    while (__hip_atomic_load(release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    while (__hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > spin_limit) {
-        s_ok = 0;
+        ok = 0;
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) break;
   }
+  if (threadIdx.x == 0) *s_ok = 1;
   __syncthreads();
-  return s_ok != 0;
-}
-
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ld_agent(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Row/column partials of the tile values in xv into set `out` (FP64 from
-// per-lane FP32 sums of at most 16 elements, fixed order).  The next grid
-// barrier makes these stores visible to the other workgroups.
-template <int BM>
-__device__ __forceinline__ void emit_partials(const float4 (&xv)[16 / (64 / (BM / 4))],
-                                              const Partials& out,
-                                              float (*s_rowred)[BM / 4 + 1], float (*s_colred)[BM],
-                                              double* s_red, int bm, int bn, int nb, int np) {
-  constexpr int NT = 4 * BM;
-  constexpr int LPR = BM / 4;
-  constexpr int RPW = 64 / LPR;
-  constexpr int STEPS = 16 / RPW;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  // Wave index as a scalar: row bounds then stay in SGPRs.
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int q = lane / LPR;
-  const int lc = lane % LPR;
-  const int cl = lc * 4;
-  float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-  for (int stp = 0; stp < STEPS; ++stp) {
-    const float4 y = xv[stp];
-    s_rowred[w * 16 + stp * RPW + q][lc] = (y.x + y.y) + (y.z + y.w);
-    cacc.x += y.x;
-    cacc.y += y.y;
-    cacc.z += y.z;
-    cacc.w += y.w;
-  }
-  *reinterpret_cast<float4*>(&s_colred[w * RPW + q][cl]) = cacc;
+  if (!ok) *s_ok = 0;
   __syncthreads();
-  const int r = tid >> 2, p = tid & 3;
-  double v = 0.0;
-#pragma unroll
-  for (int u = 0; u < LPR / 4; ++u) v += (double)s_rowred[r][p * (LPR / 4) + u];
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  if (p == 0) out.rowp[(size_t)bn * np + bm * BM + r] = v;
-  const double rowsum = (p == 0) ? v : 0.0;
-  double cv = 0.0;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) cv += (double)s_colred[p * 4 + u][r];
-  cv += __shfl_xor(cv, 1);
-  cv += __shfl_xor(cv, 2);
-  if (p == 0) out.colp[(size_t)bm * np + bn * BM + r] = cv;
-  const double tt = block_sum<NT>(rowsum, s_red);
-  if (tid == 0) out.tot[bm * nb + bn] = tt;
+  const bool all = *s_ok != 0;
+  if (threadIdx.x == 0 && all) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return all;
 }
 
 template <int BM>
 __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) {
-  constexpr int NT = 4 * BM;
-  constexpr int LPR = BM / 4;
-  constexpr int RPW = 64 / LPR;
-  constexpr int STEPS = 16 / RPW;
-  __shared__ float s_rowred[BM][LPR + 1];
+  using TS = TileShape<BM>;
+  constexpr int NT = TS::NT;
+  constexpr int LPR = TS::LPR;
+  constexpr int RPW = TS::RPW;
+  constexpr int STEPS = TS::STEPS;
+  __shared__ double s_rowsum[BM];
   __shared__ float s_colred[16][BM];
   __shared__ float s_a[BM];
   __shared__ float s_b[BM];
-  __shared__ double s_red[NT];
+  __shared__ double s_red[NT / 64];
   __shared__ double s_chain[2][4][BM];
+  __shared__ int s_ok;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -157,26 +96,26 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
   if ((G & 7) == 0) t = (t & 7) * (G >> 3) + (t >> 3);  // tile rows share an XCD
   const int bm = t / nb, bn = t % nb;
   const int q = lane / LPR;
-  const int lc = lane % LPR;
-  const int cl = lc * 4;
+  const int cl = (lane % LPR) * 4;
   const int j = bn * BM + cl;
   const bool c0 = j < n, c1 = j + 1 < n, c2 = j + 2 < n, c3 = j + 3 < n;
 
-  // ---- load the tile (rows >= n and columns >= n read as zero)
+  // ---- load the tile (rows >= n and columns >= n read as zero) and emit the
+  // partials and maximum of the input
   float4 xv[STEPS];
   float lmax = -INFINITY;
+  float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int stp = 0; stp < STEPS; ++stp) {
-    const int i = bm * BM + w * 16 + stp * RPW + q;
+    const int rl = w * 16 + stp * RPW + q;
+    const int i = bm * BM + rl;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i < n) {
-      const float* row = a.src + (size_t)i * a.ld_src + j;
-      if (a.src_vec) {
+      const float* row = &at_u32(a.src, (unsigned)(i * a.ld_src + j));
+      // A float4 only where all four columns are inside the matrix: src may
+      // have leading dimension n, so a row's tail must not be read past.
+      if (a.src_vec && c3) {
         v = *reinterpret_cast<const float4*>(row);
-        v.x = c0 ? v.x : 0.f;
-        v.y = c1 ? v.y : 0.f;
-        v.z = c2 ? v.z : 0.f;
-        v.w = c3 ? v.w : 0.f;
       } else {
         v.x = c0 ? row[0] : 0.f;
         v.y = c1 ? row[1] : 0.f;
@@ -189,60 +128,65 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
       if (c3) lmax = fmaxf(lmax, v.w);
     }
     xv[stp] = v;
+    tile_step_sums<BM>(v, rl, s_rowsum, cacc);
   }
-
-  emit_partials<BM>(xv, a.p[0], s_rowred, s_colred, s_red, bm, bn, nb, np);
+  tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.p[0].rowp, a.p[0].colp, a.p[0].tot, bm,
+                    bn, nb, np);
   {
     const float tm = block_max<NT>(lmax, reinterpret_cast<float*>(s_red));
     if (tid == 0) a.p[0].tmax[bm * nb + bn] = tm;
   }
   unsigned long long epoch = a.epoch_base + 1;
-  bool ok = grid_barrier(a.flags, epoch, a.spin_limit);
+  barrier_arrive(a.flags, epoch);
 
   int k = 1;
   double gamma = 0.0;
+  bool ok = true;
   const double dn = (double)n;
-  for (; ok; ++k) {
+  for (;; ++k) {
+    ok = barrier_wait(a.flags, epoch, a.spin_limit, &s_ok);
+    if (!ok) break;
     const Partials in = a.p[(k - 1) & 1];
     const Partials out = a.p[k & 1];
+    // All reads of the previous pass's partials are issued before any wait:
+    // the tile totals, then thread (p, r)'s chains p of row r's and column
+    // r's partial sums (combined in a fixed order after the barrier below).
     double part = 0.0;
 #pragma unroll 1
-    for (int u = tid; u < nb * nb; u += NT) part += ld_agent(in.tot + u);
+    for (int u = tid; u < nb * nb; u += NT) part += at_u32(in.tot, (unsigned)u);
+    float m = -INFINITY;
+    if (k == 1)
+      for (int u = tid; u < nb * nb; u += NT) m = fmaxf(m, at_u32(in.tmax, (unsigned)u));
+    {
+      const int r = tid % BM, p = tid / BM;
+      const unsigned ro = (unsigned)(bm * BM + r), co = (unsigned)(bn * BM + r);
+      auto ldr = [&](int b) { return at_u32(in.rowp, (unsigned)(b * np) + ro); };
+      auto ldc = [&](int b) { return at_u32(in.colp, (unsigned)(b * np) + co); };
+      s_chain[0][p][r] = chain_sum(ldr, nb, p);
+      s_chain[1][p][r] = chain_sum(ldc, nb, p);
+    }
     const double S = block_sum<NT>(part, s_red);
     float s = 1.0f;
     if (k >= 2) {
       gamma = S / dn - 1.0;
       if (gamma <= a.gamma_tol || k > a.max_passes) break;
     } else {
-      float m = -INFINITY;
-      for (int u = tid; u < nb * nb; u += NT) m = fmaxf(m, ld_agent(in.tmax + u));
       m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
       s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
     }
     const double sd = (double)s;
     const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
-    {
-      // Thread (p, r) forms chain p of row r's and column r's partial sums;
-      // the four chains are then combined in a fixed order.
-      const int r = tid % BM, p = tid / BM;
-      const double* rp = in.rowp + bm * BM + r;
-      const double* cp = in.colp + bn * BM + r;
-      auto ldr = [&](int b) { return ld_agent(rp + (size_t)b * np); };
-      auto ldc = [&](int b) { return ld_agent(cp + (size_t)b * np); };
-      s_chain[0][p][r] = chain_sum(ldr, nb, p);
-      s_chain[1][p][r] = chain_sum(ldc, nb, p);
-      __syncthreads();
-      if (tid < BM) {
-        const double ri = combine4(s_chain[0][0][tid], s_chain[0][1][tid], s_chain[0][2][tid],
-                                   s_chain[0][3][tid]);
-        const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
-                                   s_chain[1][3][tid]);
-        s_a[tid] = (float)(half - sd * ri / dn);
-        s_b[tid] = (float)(half - sd * cj / dn);
-      }
+    if (tid < BM) {
+      const double ri = combine4(s_chain[0][0][tid], s_chain[0][1][tid], s_chain[0][2][tid],
+                                 s_chain[0][3][tid]);
+      const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
+                                 s_chain[1][3][tid]);
+      s_a[tid] = (float)(half - sd * ri / dn);
+      s_b[tid] = (float)(half - sd * cj / dn);
     }
     __syncthreads();
     const float4 bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
+    cacc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int stp = 0; stp < STEPS; ++stp) {
       const int rl = w * 16 + stp * RPW + q;
@@ -256,10 +200,12 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
         y.w = c3 ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
       }
       xv[stp] = y;
+      tile_step_sums<BM>(y, rl, s_rowsum, cacc);
     }
-    emit_partials<BM>(xv, out, s_rowred, s_colred, s_red, bm, bn, nb, np);
+    tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, out.rowp, out.colp, out.tot, bm, bn, nb,
+                      np);
     ++epoch;
-    ok = grid_barrier(a.flags, epoch, a.spin_limit);
+    barrier_arrive(a.flags, epoch);
   }
   if (!ok) {
     if (tid == 0) atomicOr(&a.st->invalid, 8);
@@ -271,7 +217,7 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
 #pragma unroll
     for (int stp = 0; stp < STEPS; ++stp) {
       const int i = bm * BM + w * 16 + stp * RPW + q;
-      if (i < n) *reinterpret_cast<float4*>(a.dst + (size_t)i * np + j) = xv[stp];
+      if (i < n) *reinterpret_cast<float4*>(&at_u32(a.dst, (unsigned)(i * np + j))) = xv[stp];
     }
   }
   if (a.N != nullptr) {
@@ -286,23 +232,24 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
       if ((stp & 3) == 0) __builtin_amdgcn_sched_barrier(0);
       const int i = bm * BM + w * 16 + stp * RPW + q;
       if (i >= n) continue;
-      const size_t idx = (size_t)i * np + j;
-      const float4 o = *reinterpret_cast<const float4*>(a.N + idx);
+      const unsigned idx = (unsigned)(i * np + j);
+      float4& nref = *reinterpret_cast<float4*>(&at_u32(a.N, idx));
+      const float4 o = nref;
       const float4 d = xv[stp];
       float4 nn;
       nn.x = fmaf(alpha, d.x, c1a * o.x);
       nn.y = fmaf(alpha, d.y, c1a * o.y);
       nn.z = fmaf(alpha, d.z, c1a * o.z);
       nn.w = fmaf(alpha, d.w, c1a * o.w);
-      *reinterpret_cast<float4*>(a.N + idx) = nn;
+      nref = nn;
       if (a.nlp_kind == 1) {
-        __bf16* o16 = reinterpret_cast<__bf16*>(a.Nlp) + idx;
+        __bf16* o16 = &at_u32(reinterpret_cast<__bf16*>(a.Nlp), idx);
         o16[0] = (__bf16)nn.x;
         o16[1] = (__bf16)nn.y;
         o16[2] = (__bf16)nn.z;
         o16[3] = (__bf16)nn.w;
       } else if (a.nlp_kind == 2) {
-        _Float16* o16 = reinterpret_cast<_Float16*>(a.Nlp) + idx;
+        _Float16* o16 = &at_u32(reinterpret_cast<_Float16*>(a.Nlp), idx);
         o16[0] = (_Float16)nn.x;
         o16[1] = (_Float16)nn.y;
         o16[2] = (_Float16)nn.z;
