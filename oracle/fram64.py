@@ -5,7 +5,8 @@ benchmark's CPU-baseline leg; never by the library or its binding.
 
 Every function follows the paper's algorithms in their order and notation:
 
-* ``prescale``   -- Algorithm 1, steps 2-3 (global max c, divide A, A~ by sqrt(c)).
+* ``prescale``   -- Algorithm 1, steps 2-3 (global max c, divide A, A~ by sqrt(c)
+                    and the node similarities K by c).
 * ``p1``         -- the affine projection P1 onto {Y1 = 1, Y^T 1 = 1}, eq. (P1_sol)
                     in Sec. 5.1 (proved for asymmetric X in Theorem 5, App. D).
 * ``p2``         -- the nonnegativity projection P2(X) = (X + |X|)/2, Sec. 5.1.
@@ -17,8 +18,9 @@ Every function follows the paper's algorithms in their order and notation:
 * ``discretize`` -- Algorithm 1 step 10 / eq. (2): the linear assignment
                     M = argmin_P ||P - N||_F, i.e. argmax_P <P, N>, by an exact LAP
                     solver (scipy's linear_sum_assignment).
-* ``objective``  -- twice Phi(M) of eq. (1) without node attributes:
-                    sum_{k,l} A_kl B_{s(k) s(l)} = tr(A M B M^T) on the unscaled input.
+* ``objective``  -- twice Phi(M) of eq. (1): sum_{k,l} A_kl B_{s(k) s(l)}
+                    = tr(A M B M^T), plus 2 lam <M, K> with node similarities,
+                    on the unscaled input.
 
 Readings of points where the paper is silent or ambiguous (each one is also
 listed with its justification in the design notes):
@@ -27,7 +29,8 @@ listed with its justification in the design notes):
   gradient is the zero matrix; SDSN of a matrix whose max is <= 0 starts from
   the zero matrix, and P1(0) = 11^T/n, so D^(1) = 11^T/n.
 * "lambda" at the library boundary is the SDSN strength theta; the node-term
-  weight multiplies K = F F~^T which is absent here (no node attributes).
+  weight is ``lam`` and multiplies K = F F~^T (optional; n = n~ only, the
+  paper's own simplification in Sec. 3).
 * gamma is evaluated on each pass output (Sec. 5.2 definition), at least one
   pass is made, and the loop stops when gamma <= gamma_th or at a pass cap.
 * The outer loop is a do-while: stop when delta <= tol or after ``iters``
@@ -43,13 +46,21 @@ from scipy.optimize import linear_sum_assignment
 
 
 # ---------------------------------------------------------------- Alg. 1, steps 2-3
-def prescale(A: np.ndarray, B: np.ndarray):
-    """c = max(A, A~) (K is absent), then A/sqrt(c), A~/sqrt(c) -- Alg. 1 steps 2-3."""
+def prescale(A: np.ndarray, B: np.ndarray, K: np.ndarray | None = None):
+    """c = max(A, A~, K), then A/sqrt(c), A~/sqrt(c), K/c -- Alg. 1 steps 2-3.
+
+    Returns (A/sqrt(c), A~/sqrt(c), c) without K, (A/sqrt(c), A~/sqrt(c), K/c, c)
+    with it.  A non-positive c leaves the inputs unscaled."""
     c = max(float(A.max()), float(B.max()))
+    if K is not None:
+        c = max(c, float(np.max(K)))
     if c <= 0.0:
-        return A.astype(np.float64).copy(), B.astype(np.float64).copy(), c
+        out = (A.astype(np.float64).copy(), B.astype(np.float64).copy())
+        return (*out, c) if K is None else (*out, np.asarray(K, dtype=np.float64).copy(), c)
     s = math.sqrt(c)
-    return A / s, B / s, c
+    if K is None:
+        return A / s, B / s, c
+    return A / s, B / s, np.asarray(K, dtype=np.float64) / c, c
 
 
 # ---------------------------------------------------------------- Sec. 5.1 projections
@@ -128,10 +139,13 @@ class FramInfo:
 
 def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
          iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6,
-         sdsn_max: int = 1000, N0: np.ndarray | None = None, stable_iters: int = 0):
+         sdsn_max: int = 1000, N0: np.ndarray | None = None, stable_iters: int = 0,
+         K: np.ndarray | None = None, lam: float = 1.0):
     """Algorithm 1 up to (not including) the discretisation of step 10.
 
-    Returns (N, FramInfo).  A and B are the *unscaled* inputs.
+    Returns (N, FramInfo).  A and B are the *unscaled* inputs.  K (n x n) is
+    the node-similarity matrix F F~^T of eq. (1), weighted by lam in the
+    gradient of eq. (3) (step 5: X = A N A~ + lam K); None means no node term.
 
     stable_iters = w > 0 adds a second stop (not in the paper, whose delta_th
     is unspecified): stop once the row argmax of N (lowest column on ties)
@@ -141,7 +155,11 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
     """
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
-    As, Bs, _ = prescale(A, B)
+    if K is None:
+        As, Bs, _ = prescale(A, B)
+        Ks = None
+    else:
+        As, Bs, Ks, _ = prescale(A, B, np.asarray(K, dtype=np.float64))
     n = A.shape[0]
     N = np.zeros((n, n)) if N0 is None else np.array(N0, dtype=np.float64)
     passes, deltas, gammas = [], [], []
@@ -149,7 +167,9 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
     t = 0
     prev_arg, same = None, 0
     while True:
-        X = As @ N @ Bs                                       # step 5 (K absent)
+        X = As @ N @ Bs                                       # step 5
+        if Ks is not None:
+            X = X + lam * Ks
         D, info = sdsn(X, theta, gamma_th, sdsn_max)           # step 6
         N_new = (1.0 - alpha) * N + alpha * D                  # step 7
         num = np.linalg.norm(N_new - N)                        # step 8
@@ -189,10 +209,18 @@ def discretize(N: np.ndarray) -> np.ndarray:
     return sigma
 
 
-def objective(A: np.ndarray, B: np.ndarray, sigma: np.ndarray) -> float:
-    """sum_{k,l} A_kl B_{sigma(k) sigma(l)} = tr(A M B M^T) = 2 Phi(M) without node term (eq. 1)."""
+def objective(A: np.ndarray, B: np.ndarray, sigma: np.ndarray, K: np.ndarray | None = None,
+              lam: float = 1.0) -> float:
+    """Twice Phi(M) of eq. (1) on the unscaled inputs, M the permutation sigma:
+    sum_{k,l} A_kl B_{sigma(k) sigma(l)} (= tr(A M B M^T)) plus, with node
+    similarities K, 2 lam sum_k K_{k, sigma(k)} (= 2 lam <M, K>)."""
     sigma = np.asarray(sigma)
-    return float(np.sum(np.asarray(A, dtype=np.float64) * np.asarray(B, dtype=np.float64)[np.ix_(sigma, sigma)]))
+    edge = float(np.sum(np.asarray(A, dtype=np.float64) *
+                        np.asarray(B, dtype=np.float64)[np.ix_(sigma, sigma)]))
+    if K is None:
+        return edge
+    node = float(np.sum(np.asarray(K, dtype=np.float64)[np.arange(len(sigma)), sigma]))
+    return edge + 2.0 * lam * node
 
 
 def accuracy(sigma: np.ndarray, perm: np.ndarray, inlier: np.ndarray | None = None) -> float:
@@ -205,8 +233,9 @@ def accuracy(sigma: np.ndarray, perm: np.ndarray, inlier: np.ndarray | None = No
 
 def solve(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
           iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6, sdsn_max: int = 1000,
-          stable_iters: int = 0):
+          stable_iters: int = 0, K: np.ndarray | None = None, lam: float = 1.0):
     """Full FRAM: Algorithm 1 including step 10; returns (sigma, objective, N, FramInfo)."""
-    N, info = fram(A, B, theta, alpha, iters, tol, gamma_th, sdsn_max, stable_iters=stable_iters)
+    N, info = fram(A, B, theta, alpha, iters, tol, gamma_th, sdsn_max, stable_iters=stable_iters,
+                   K=K, lam=lam)
     sigma = discretize(N)
-    return sigma, objective(A, B, sigma), N, info
+    return sigma, objective(A, B, sigma, K, lam), N, info

@@ -7,6 +7,8 @@ the HIP path can share inputs without sharing any step of the method.
 """
 from .graphs import (  # noqa: F401
     GraphPair,
+    AttributedPair,
+    make_attributed_pair,
     er_adjacency,
     permuted_noisy_copy,
     make_pair,

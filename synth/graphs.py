@@ -20,6 +20,12 @@ Conventions (fixed here, shared by every consumer):
   correspondence is only meaningful on the remaining (inlier) nodes.
 
 Seeds: pair ``i`` of workload ``c`` uses ``numpy.random.default_rng(1000*c + i)``.
+
+Attributed pairs (node term of eq. 1) add nonnegative node features: F is
+n x d with U(0,1) entries and unit-norm rows (descriptor-like histograms), the
+second graph's features are the relabelled copy plus clipped Gaussian noise,
+and K = F F~^T is their similarity matrix (K[k, perm[k]] is largest when the
+noise is small).
 """
 from __future__ import annotations
 
@@ -110,6 +116,27 @@ def make_pair(n: int, p: float, sigma: float, seed: int, weights: str = "open",
     A = er_adjacency(rng, n, p, weights)
     B, perm, inlier = permuted_noisy_copy(rng, A, sigma, delete_frac, outlier_frac, p)
     return GraphPair(A=A, B=B, perm=perm, inlier=inlier, seed=seed)
+
+
+@dataclasses.dataclass
+class AttributedPair(GraphPair):
+    K: np.ndarray | None = None   # (n, n) float64 node similarities F F~^T, >= 0
+
+
+def make_attributed_pair(n: int, p: float, sigma: float, seed: int, d: int = 16,
+                         feat_sigma: float = 0.05, weights: str = "open") -> AttributedPair:
+    """A noisy relabelled pair (as make_pair, no deletions or outliers) with
+    node features; see the module notes for K."""
+    base = make_pair(n, p, sigma, seed, weights)
+    rng = np.random.default_rng(seed + 7_000_000)
+    F = rng.random((n, d))
+    F /= np.linalg.norm(F, axis=1, keepdims=True)
+    Ft = np.empty_like(F)
+    Ft[base.perm] = F
+    if feat_sigma > 0:
+        Ft = np.maximum(Ft + rng.normal(0.0, feat_sigma, Ft.shape), 0.0)
+    return AttributedPair(A=base.A, B=base.B, perm=base.perm, inlier=base.inlier,
+                          seed=seed, K=F @ Ft.T)
 
 
 def config_sizes(config: int) -> dict:
