@@ -10,6 +10,13 @@ seed 2000), with A and B resident in HBM before timing starts
 also timed with FP32 GEMMs, and one extra profiled solve of each precision
 gives per-kernel device times from HIP events on the library's stream.
 
+Two further legs run after it (each can be switched off):
+* batched: 512 independent pairs, n ~ U{20..300}, in one fram_solve_many call
+  (pairs/s, inputs uploaded inside the timed call);
+* served: Poisson arrivals at 200 requests/s for 30 s after a 5 s warm-up,
+  n log-uniform in [30, 2000], through the continuous-batching server
+  (p50 / p99 latency from arrival to result, completed requests/s).
+
 Prints one JSON line.  Only one GPU is supported (--gpus 1).
 """
 from __future__ import annotations
@@ -31,6 +38,7 @@ THETA, ITERS, TOL, GAMMA_TOL = 2.0, 100, 1e-6, 1e-6
 # off near 1e-4 and FP32 near 1e-6, above the tolerance the FP64 oracle reaches.
 STABLE_ITERS = 3
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
 
 
@@ -77,6 +85,84 @@ def cpu_baseline(pair, T, P, source):
     }
 
 
+def measured_traffic(kind, n, passes_per_launch):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a
+    plain copy of known size), or None when the summary is missing or was
+    taken from a different version of the kernel's sources."""
+    f = ROOT / "profiles" / "hbm_traffic.json"
+    if not f.exists():
+        return None
+    try:
+        rec = json.loads(f.read_text()).get(kind)
+        if rec is None or rec.get("n") != n:
+            return None
+        if rec.get("source_sha256") != kernel_source_hash():
+            return None
+        return rec["bytes_per_launch"]
+    except (ValueError, KeyError):
+        return None
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("sdsn_persistent.hip", "sdsn.hip", "sdsn_common.h"):
+        h.update((ROOT / "paper_2508_00887_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
+def batched_leg(Context, reps=2):
+    """C3: one fram_solve_many call over 512 pairs; best of `reps` calls."""
+    import numpy as np
+    import synth
+    pairs = synth.batched_pairs(512)
+    ctx = Context(0)
+    best, out = None, None
+    for r in range(reps):
+        t0 = time.perf_counter()
+        perms, objs, stats = ctx.solve_many([q.A for q in pairs], [q.B for q in pairs],
+                                            theta=THETA, iters=ITERS, tol=TOL, prec="bf16",
+                                            stable_iters=STABLE_ITERS)
+        dt = time.perf_counter() - t0
+        log(f"batched call {r + 1}/{reps}: {dt:.3f}s")
+        if best is None or dt < best:
+            best, out = dt, (perms, stats)
+    ctx.close()
+    perms, stats = out
+    return {
+        "pairs": len(pairs), "seconds": best, "pairs_per_s": len(pairs) / best,
+        "mean_accuracy": float(np.mean([np.mean(p == q.perm) for p, q in zip(perms, pairs)])),
+        "mean_outer_iters": float(np.mean([s["outer_iters"] for s in stats])),
+        "assignments_with_paths": int(sum(1 for s in stats if s["lap_paths"] > 0)),
+        "gemm_precision": "bf16",
+    }
+
+
+def served_leg(rate=200.0, duration_s=30.0, warmup_s=5.0, pool=160):
+    """C4 through paper_2508_00887_amd.serve.  Graph generation for every
+    request would outrun host memory (about 50 GB), so the first `pool` sizes
+    of the trace are generated once and request i solves pool[i % pool]; the
+    arrival times and the size distribution are those of the trace."""
+    import numpy as np
+    import synth
+    from paper_2508_00887_amd.serve import Request, Server, summarize
+    trace = synth.serve_requests(rate, duration_s, warmup_s)
+    graphs = [synth.make_pair(n, 0.3, 0.05, seed) for _, n, seed in trace[:pool]]
+    log(f"served: {len(trace)} requests, {len(graphs)} distinct graphs generated")
+    reqs = [Request(rid=i, A=graphs[i % pool].A, B=graphs[i % pool].B, arrival=t)
+            for i, (t, _, _) in enumerate(trace)]
+    srv = Server(hbm_budget_bytes=64 << 30, prec="bf16", theta=THETA, iters=ITERS, tol=TOL,
+                 stable_iters=STABLE_ITERS)
+    done = srv.replay(reqs, timeout_s=warmup_s + duration_s + 120.0)
+    summ = summarize(done, warmup_s, duration_s)
+    acc = [float(np.mean(r.perm == graphs[r.rid % pool].perm)) for r in done if r.perm is not None]
+    summ.update(offered_rate=rate, duration_s=duration_s, warmup_s=warmup_s,
+                completed=len(done), submitted=len(reqs), distinct_graphs=len(graphs),
+                mean_accuracy=float(np.mean(acc)) if acc else None, gemm_precision="bf16")
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +172,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sdsn-mode", default="auto", choices=["auto", "stream", "onchip"])
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the FRAM hot path here is a single-GPU build "
@@ -94,6 +185,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # A plain copy of known size: reads and writes COPY_BYTES per launch.
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": COPY_BYTES, "launches": 3}), flush=True)
+        return
 
     import synth
     from paper_2508_00887_amd import Context
@@ -106,57 +207,63 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     ctx = Context(0)
 
-    def solve(prec, profile=False):
+    def solve(prec, profile=0):
         return ctx.solve_dev(dA.data_ptr(), dB.data_ptr(), n, theta=THETA, iters=ITERS, tol=TOL,
                              prec=prec, gamma_tol=GAMMA_TOL, stream=stream, profile=profile,
                              stable_iters=STABLE_ITERS, sdsn_mode=args.sdsn_mode)
 
+    keys = ("ms_gemm", "gemm_launches", "ms_sdsn", "sdsn_launches", "sdsn_passes", "ms_update",
+            "ms_stats", "outer_iters")
+
     def timed(prec, steps, warmup):
+        """Wall time per solve over `steps` solves; the library records HIP
+        events around its launches on the solve's stream during the same
+        solves (profile = 2: recorded, not waited for)."""
         for w in range(warmup):
             solve(prec)
             log(f"warmup {prec} {w + 1}/{warmup} done")
         torch.cuda.synchronize()
+        tot = dict.fromkeys(keys, 0.0)
         t0 = time.perf_counter()
         out = None
         for s in range(steps):
-            out = solve(prec)
+            out = solve(prec, profile=2)
+            for k in keys:
+                tot[k] += out[2][k]
             log(f"step {prec} {s + 1}/{steps} done")
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, out
+        sec = (time.perf_counter() - t0) / steps
+        flops = 4.0 * n ** 3 * tot["outer_iters"]
+        prof = dict(
+            gemm_tflops=flops / (tot["ms_gemm"] * 1e-3) / 1e12,
+            gemm_us_per_launch=1e3 * tot["ms_gemm"] / max(1, tot["gemm_launches"]),
+            sdsn_launches=int(tot["sdsn_launches"]), sdsn_passes=int(tot["sdsn_passes"]),
+            sdsn_us_per_launch=1e3 * tot["ms_sdsn"] / max(1, tot["sdsn_launches"]),
+            sdsn_us_per_pass=1e3 * tot["ms_sdsn"] / max(1, tot["sdsn_passes"]),
+            ms_per_solve={k: tot[k] / steps for k in ("ms_gemm", "ms_sdsn", "ms_update",
+                                                      "ms_stats")},
+        )
+        return sec, out, prof
 
-    sec_mixed, (perm, obj, st) = timed(args.prec, args.steps, args.warmup)
+    sec_mixed, (perm, obj, st), pm = timed(args.prec, args.steps, args.warmup)
     acc = float(np.mean((perm == pair.perm)[pair.inlier]))
     res = {}
+    prof = {args.prec: pm}
     if not args.no_fp32:
-        sec32, (perm32, obj32, st32) = timed("fp32", max(1, args.steps // 2), 1)
+        sec32, (perm32, obj32, st32), prof["fp32"] = timed("fp32", max(1, args.steps // 2), 1)
         res["fp32"] = dict(solves_per_s=1.0 / sec32, ms_per_solve=1e3 * sec32,
                            outer_iters=st32["outer_iters"], sdsn_passes=st32["sdsn_passes"],
                            objective=obj32,
                            accuracy=float(np.mean((perm32 == pair.perm)[pair.inlier])))
-    # Profiled solves: per-kernel device time (HIP events on the solve's stream).
-    prof = {}
-    for prec in [args.prec] + ([] if args.no_fp32 else ["fp32"]):
-        _, _, sp = solve(prec, profile=True)
-        log(f"profiled {prec} solve done")
-        flops = 4.0 * n ** 3 * sp["outer_iters"]
-        launches = sp["outer_iters"] if sp["ms_stats"] == 0.0 else sp["sdsn_launches"]
-        prof[prec] = dict(
-            gemm_tflops=flops / (sp["ms_gemm"] * 1e-3) / 1e12,
-            gemm_ms_per_launch=sp["ms_gemm"] / max(1, sp["gemm_launches"]),
-            sdsn_passes=sp["sdsn_launches"],
-            sdsn_launches=launches,
-            sdsn_us_per_pass=1e3 * sp["ms_sdsn"] / max(1, sp["sdsn_launches"]),
-            sdsn_us_per_launch=1e3 * sp["ms_sdsn"] / max(1, launches),
-            ms_gemm=sp["ms_gemm"], ms_sdsn=sp["ms_sdsn"], ms_stats=sp["ms_stats"],
-            ms_update=sp["ms_update"], outer_iters=sp["outer_iters"],
-        )
-    pm = prof[args.prec]
     # Algorithmic bytes of one SDSN pass: read X and write Y once (8 n^2).  The
     # on-chip variant runs a whole projection per launch and keeps X in VGPRs,
     # so its effective rate can exceed the HBM roofline.
     pass_bytes = 8.0 * n * n
     bytes_per_launch = pass_bytes * pm["sdsn_passes"] / max(1, pm["sdsn_launches"])
     achieved = bytes_per_launch / (pm["sdsn_us_per_launch"] * 1e-6) / 1e9
+    onchip = pm["sdsn_launches"] != pm["sdsn_passes"]
+    traffic = measured_traffic("sdsn_onchip" if onchip else "sdsn_stream", n,
+                               pm["sdsn_passes"] / max(1, pm["sdsn_launches"]))
     golden = ROOT / "tests" / "golden" / "fram_c2_seed2000.json"
     rel_err, g = None, None
     if golden.exists():
@@ -177,15 +284,17 @@ def main():
                    "gemm_precision": args.prec, "sdsn_mode": args.sdsn_mode},
         "outer_iters": st["outer_iters"], "sdsn_passes": st["sdsn_passes"],
         "accuracy": acc, "objective": obj, "rel_obj_err_vs_oracle": rel_err,
-        "host_lap": st["host_lap"],
+        "lap_paths": st["lap_paths"],
         "gemm_tflops": {k: v["gemm_tflops"] for k, v in prof.items()},
         "profile": prof,
-        "roofline": {"bound": "hbm", "kernel": "sdsn (" + ("on-chip projection" if
-                     pm["sdsn_launches"] != pm["sdsn_passes"] else "streaming pass") + ")",
+        "roofline": {"bound": "hbm",
+                     "kernel": "sdsn_persistent_kernel (one launch per projection)" if onchip
+                     else "sdsn tile_kernel (one launch per pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": pm["sdsn_us_per_launch"]},
+                     "avg_launch_us": pm["sdsn_us_per_launch"],
+                     "passes_per_launch": pm["sdsn_passes"] / max(1, pm["sdsn_launches"])},
         "oracle_accuracy": g["accuracy"] if g else None,
         "oracle_outer_iters": g["outer_iters"] if g else None,
         "stop_rule": {"tol": TOL, "stable_iters": STABLE_ITERS, "iters_cap": ITERS},
@@ -193,6 +302,12 @@ def main():
     if "fp32" in res:
         line["fp32"] = res["fp32"]
         line["speedup_vs_fp32"] = line["value"] / res["fp32"]["solves_per_s"]
+    if not args.no_batched:
+        log("batched leg: 512 pairs")
+        line["batched"] = batched_leg(Context)
+    if not args.no_serve:
+        log("served leg")
+        line["served"] = served_leg(duration_s=args.serve_seconds)
     if not args.no_cpu_baseline:
         if g is not None:
             T, P, src = g["outer_iters"], int(sum(g["sdsn_passes"])), "the oracle's stored run"

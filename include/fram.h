@@ -73,16 +73,20 @@ typedef struct {
   int sdsn_passes_max;   /* largest pass count of any outer iteration                  */
   int converged;         /* 1 if delta <= tol stopped the loop                         */
   int sdsn_capped;       /* 1 if some SDSN call hit sdsn_max with gamma > gamma_tol    */
-  int host_lap;          /* 1 if the row argmax of N was not a permutation and the
-                            exact assignment was computed by the library's host solver */
+  int lap_paths;         /* augmenting paths the final assignment needed: 0 when the row
+                            argmax of N was already a permutation (see fram_assign)   */
   int gemm_tile;         /* GEMM / SDSN tile edge used (64, 128 or 256)                 */
   double delta;          /* last delta (App. B.2)                                      */
   double gamma;          /* gamma of the last SDSN output (Sec. 5.2)                   */
   double ms_total;       /* wall time of the call on the host, milliseconds            */
-  /* Filled only when fram_options.profile = 1 (HIP events around each launch,
-   * launches serialised): summed device milliseconds and launch counts. */
+  /* Filled only when fram_options.profile is 1 or 2 (HIP events around each
+   * launch on the solve's stream): summed device milliseconds and launch counts.
+   * profile = 1 waits for every launch (each time is that launch alone);
+   * profile = 2 only records the events and reads them after the solve, so
+   * launches keep their normal pacing (streaming SDSN passes are then timed
+   * per enqueued chunk). */
   int gemm_launches;     /* GEMM launches (two per outer iteration)                    */
-  int sdsn_launches;     /* SDSN pass launches that did work                           */
+  int sdsn_launches;     /* SDSN launches that did work (on-chip: one per projection)  */
   double ms_gemm;        /* GEMM 1 + GEMM 2                                            */
   double ms_sdsn;        /* SDSN passes (excluding the final gamma check)              */
   double ms_stats;       /* tile statistics of X that start each SDSN call            */
@@ -95,7 +99,8 @@ typedef struct {
   double gamma_tol;      /* SDSN stop: gamma <= gamma_tol; default 1e-6                */
   int sdsn_max;          /* SDSN pass cap per call; default 1000                       */
   int tile;              /* 0 = automatic, else 64 / 128 / 256                          */
-  int profile;           /* 1 = time kernels with HIP events into fram_stats (slower)  */
+  int profile;           /* 0 = off; 1 = time each launch alone; 2 = time launches
+                            without serialising them (see fram_stats)                 */
   int stable_iters;      /* w > 0: also stop once the row argmax of N has been the same
                             permutation for w consecutive iterations (a second stop
                             rule beside delta <= tol, for precisions whose delta
@@ -181,14 +186,47 @@ fram_status fram_sdsn_project_dev(fram_ctx* ctx, const float* dK, int ldk, int n
 fram_status fram_gradient(fram_ctx* ctx, const float* A, const float* N, const float* B,
                           int n, fram_precision prec, float* X_out);
 
-/* Exact linear assignment of Algorithm 1 step 10 / eq. (2) on a host matrix:
- * perm_out maximises sum_i W[i, perm_out[i]], which is the permutation P
- * minimising ||P - W||_F.  W: host, n*n floats, row-major, finite.
- * perm_out: host, n int32 (written).  Runs on the host CPU (shortest
- * augmenting paths with dual potentials, the Hungarian method); the solvers
- * use it only when the device row argmax of N is not already a permutation
- * (a row argmax that is a permutation is the exact optimum). */
-fram_status fram_assign(const float* W, int n, int32_t* perm_out);
+/* FRAM on attributed graphs: the node term of eq. (1), lambda <N, K> with
+ * K = F F~^T (Sec. 3), enters every gradient of eq. (3) / Algorithm 1 step 5:
+ * X = A N A~ + node_weight K.  Algorithm 1 steps 2-3 scale K with the edges
+ * (here: by 1 / (max A max A~), which differs from the paper's c-scaling only
+ * by a positive factor common to both terms, which SDSN divides out).
+ *   K            n*n doubles, row-major, finite (any sign, need not be
+ *                symmetric); host for _ex, device for _dev.
+ *   node_weight  the lambda of eq. (1) (the paper uses 1); finite.
+ *   objective_out = 2 Phi(M) = sum_{k,l} A_kl B_{s(k)s(l)} + 2 node_weight
+ *                sum_k K[k, s(k)], in FP64 on the unscaled inputs.
+ * n = n~ as in the paper's formulation (Sec. 3).  Everything else as
+ * fram_solve_ex / fram_solve_dev (lambda there is the SDSN strength theta). */
+fram_status fram_solve_attr_ex(fram_ctx* ctx, const double* A, const double* B, const double* K,
+                               int n, double node_weight, double lambda, int iters, double tol,
+                               const fram_options* opt, int32_t* perm_out, double* objective_out,
+                               fram_stats* stats);
+
+fram_status fram_solve_attr_dev(fram_ctx* ctx, const double* dA, const double* dB,
+                                const double* dK, int n, double node_weight, double lambda,
+                                int iters, double tol, const fram_options* opt, int32_t* perm_out,
+                                double* objective_out, fram_stats* stats, void* stream);
+
+/* Exact linear assignment of Algorithm 1 step 10 / eq. (2), the discretisation
+ * the paper does with the Hungarian method (Sec. 6): perm_out maximises
+ * sum_i W[i, perm_out[i]], i.e. it is the permutation P minimising ||P - W||_F.
+ * Runs on the device: row maxima as the starting duals, then one shortest
+ * augmenting path (with row/column potentials) per row whose maximum collides
+ * with a lower-numbered row's; when the row argmax is already a permutation
+ * it is returned as is.  Ties go to the lowest column.  The solvers use the
+ * same device code for their final step.
+ *   W        host, n*n floats, row-major, finite (else FRAM_EINVAL).
+ *   perm_out host, n int32 (written).
+ * fram_last_stats().lap_paths reports the augmenting paths taken. */
+fram_status fram_assign(fram_ctx* ctx, const float* W, int n, int32_t* perm_out);
+
+/* Same on device memory: dW n x n floats with leading dimension ldw >= n,
+ * dperm n int32 (written), on `stream` (a hipStream_t; NULL = the context's
+ * stream).  Returns after the stream has finished the assignment.  A matrix
+ * with non-finite entries gives FRAM_ENUMERIC and dperm filled with -1. */
+fram_status fram_assign_dev(fram_ctx* ctx, const float* dW, int ldw, int n, int32_t* dperm,
+                            void* stream);
 
 /* Many independent pairs (uneven n) solved in one batched device launch.
  *   count        >= 1 pairs; A[i], B[i] host n[i]*n[i] doubles.

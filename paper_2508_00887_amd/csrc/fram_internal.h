@@ -20,12 +20,14 @@ struct DevState {
   int capped;        // some projection hit the pass cap (on-chip SDSN path)
   int arg_perm;      // row argmax of N is a permutation (argmax tracking)
   int arg_same;      // ... and equals the previous iteration's argmax
+  int lap_paths;     // augmenting paths of the final assignment (-1: failed)
   double gamma;      // gamma of the last SDSN output
   double delta;      // delta of the last outer update
   double dnum;       // ||N_new - N_old||_F^2 of the last update
   double dden;       // ||N_new||_F^2 of the last update
   double maxA;       // max entry of A (unscaled)
   double maxB;       // max entry of B (unscaled)
+  double maxK;       // max |entry| of the node similarities K (unscaled)
   double objective;  // sum_{k,l} A_kl B_{s(k)s(l)}
 };
 
@@ -51,11 +53,12 @@ inline size_t elem_size(Elem e) { return e == Elem::F32 ? 4 : 2; }
 
 // C (np x np) = P (np x np) * Q^T over K = n (rounded up to the K step),
 // inputs of type e, FP32 accumulation.
-// C is written as type e when c_f32 == false, as float otherwise.  np must be
-// a multiple of bm (64, 128 or 256); all padding rows/columns of P and Q must
-// be zero up to np.
+// C is written as type e when c_f32 == false, as float otherwise; with
+// c_f32, an optional FP32 matrix `bias` (same layout as C) is added to every
+// output.  np must be a multiple of bm (64, 128 or 256); all padding
+// rows/columns of P and Q must be zero up to np.
 hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
-                          int n, int np, int ld, hipStream_t s);
+                          int n, int np, int ld, hipStream_t s, const float* bias = nullptr);
 
 // Tile statistics of an n x n matrix: reads src (ld_src), writes it padded to
 // dst (np x np, ld np, zero padding) unless dst == nullptr or dst == src, and
@@ -117,7 +120,9 @@ struct BatchPair {
 struct BatchResult {
   double objective, delta, gamma;
   int outer_iters, sdsn_passes, sdsn_passes_max, sdsn_passes_last;
-  int converged, sdsn_capped, is_perm, pad;
+  int converged, sdsn_capped;
+  int is_perm;    // the final row argmax was a permutation
+  int lap_paths;  // else: rows that needed an augmenting path (-1: failed)
 };
 
 struct BatchArgs {
@@ -130,7 +135,6 @@ struct BatchArgs {
   double theta, alpha, gamma_tol, tol;
   int iters, sdsn_max;
   int stable_iters;     // argmax-stability stop (0 = off)
-  int objective_only;   // 1: only recompute objectives from sigma (after host assignment)
 };
 
 constexpr int kBatchMaxN = 512;  // largest pair the batched kernel takes
@@ -155,6 +159,15 @@ int max_blocks(int n);
 hipError_t launch_cast_scaled(Elem e, const double* src, int n, void* dst, int np,
                               const DevState* st, int which, hipStream_t s);
 
+// Node term of the gradient: dst (np x np FP32) = w K / (maxA maxB), the
+// node similarities on the same scale as the scaled edge term (falls back to
+// w K / max|K| when a graph has no edges), zero padding.  Computes st->maxK.
+hipError_t launch_node_term(const double* K, int n, double w, float* dst, int np, double* part,
+                            int nblocks, DevState* st, hipStream_t s);
+// st->objective += 2 w sum_k K[k, sigma(k)] (FP64), after launch_objective.
+hipError_t launch_node_objective(const double* K, const int32_t* sigma, int n, double w,
+                                 DevState* st, hipStream_t s);
+
 // dst (np x np, type e) = src (n x n float, ld n), no scaling, zero padding.
 hipError_t launch_cast_f32(Elem e, const float* src, int n, void* dst, int np, hipStream_t s);
 
@@ -164,8 +177,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Validation of device inputs: sets bits of st->invalid.
 hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s);
 
-// sigma[i] = argmax_j N[i, j] (lowest j on ties), i < n.
-hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s);
+// sigma[i] = argmax_j N[i, j] (lowest j on ties), i < n; if u is not null,
+// also u[i] = -max_j N[i, j] in FP64 (the assignment's starting duals).
+hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s,
+                             double* u = nullptr);
 
 // Argmax tracking for the stability stop: cur (written by row_argmax) is
 // checked for being a permutation and compared with prev; then prev = cur.
@@ -183,8 +198,28 @@ int objective_blocks(int n);
 hipError_t launch_copy_f32(const float* src, int ld_src, float* dst, int ld_dst, int n,
                            hipStream_t s);
 
-// Host exact linear assignment: maximise sum_i W[i, sigma(i)], W n x n
-// row-major doubles.  sigma_init may hold a partial assignment (-1 = free).
-void host_lap_max(const float* W, int n, int ld, const int32_t* sigma_init, int32_t* sigma);
+// ------------------------------------------------------- device assignment
+// One exact linear assignment problem: maximise sum_i w[i, sigma(i)] over
+// permutations, w n x n row-major FP32 (leading dimension ld).  sigma
+// receives the optimal assignment (all -1 if w admits no finite one); on
+// entry it must hold the row argmax of w (lowest column on ties) when
+// u_ready is set, and u_init[i] = -max_j w[i, j] in FP64 (may point into ws);
+// otherwise the kernel computes both.  ws: lap_workspace_bytes(n) bytes of
+// device memory.  paths_out (may be null) receives the number of rows that
+// needed an augmenting path (0 when the row argmax is a permutation), or -1.
+struct LapProblem {
+  const float* w;
+  int n, ld;
+  int32_t* sigma;
+  char* ws;
+  const double* u_init;
+  int u_ready;
+  int* paths_out;
+};
+size_t lap_workspace_bytes(int n);
+// Solves `count` problems, one workgroup each: either the single problem
+// *one (count == 1) or the device array probs.  max_n bounds every n.
+hipError_t launch_lap(const LapProblem* one, const LapProblem* probs, int count, int max_n,
+                      hipStream_t s);
 
 }  // namespace fram

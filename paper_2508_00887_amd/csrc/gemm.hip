@@ -77,8 +77,9 @@ __device__ __forceinline__ int swz(int row, int ch) { return ch ^ (row & 7); }
 template <Elem E, int BM, bool OUT_F32>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
                                                       const v4u* __restrict__ Q,
-                                                      void* __restrict__ C, int np, int ld,
-                                                      int ktiles) {
+                                                      void* __restrict__ C,
+                                                      const float* __restrict__ bias, int np,
+                                                      int ld, int ktiles) {
   constexpr int WT = BM / 2;          // wave tile edge
   constexpr int F = WT / 32;          // MFMA blocks per wave tile edge
   constexpr int LOADS = BM * kChunks / 256;
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
         for (int r = 0; r < 4; ++r) {
           const size_t row = (size_t)(m0 + wm * WT + i * 32 + 8 * g + 4 * half + r);
           const size_t col = (size_t)(n0 + wn * WT + j * 32 + l32);
-          const float v = acc[i][j][4 * g + r];
+          float v = acc[i][j][4 * g + r];
+          if (OUT_F32 && bias != nullptr) v += bias[row * ld + col];
           if (OUT_F32)
             reinterpret_cast<float*>(C)[row * ld + col] = v;
           else
@@ -198,8 +200,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
 }
 
 template <Elem E, bool OUT_F32>
-hipError_t launch_e(int bm, const void* P, const void* Q, void* C, int n, int np, int ld,
-                    hipStream_t s) {
+hipError_t launch_e(int bm, const void* P, const void* Q, void* C, const float* bias, int n,
+                    int np, int ld, hipStream_t s) {
   const int kelems = kChunks * Mfma<E>::kPerChunk;
   const int ktiles = (n + kelems - 1) / kelems;
   const int nb = np / bm;
@@ -208,13 +210,13 @@ hipError_t launch_e(int bm, const void* P, const void* Q, void* C, int n, int np
   const v4u* q = static_cast<const v4u*>(Q);
   switch (bm) {
     case 64:
-      gemm_nt_kernel<E, 64, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      gemm_nt_kernel<E, 64, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
       break;
     case 128:
-      gemm_nt_kernel<E, 128, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      gemm_nt_kernel<E, 128, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
       break;
     case 256:
-      gemm_nt_kernel<E, 256, OUT_F32><<<grid, block, 0, s>>>(p, q, C, np, ld, ktiles);
+      gemm_nt_kernel<E, 256, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
       break;
     default:
       return hipErrorInvalidValue;
@@ -225,17 +227,18 @@ hipError_t launch_e(int bm, const void* P, const void* Q, void* C, int n, int np
 }  // namespace
 
 hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
-                          int n, int np, int ld, hipStream_t s) {
+                          int n, int np, int ld, hipStream_t s, const float* bias) {
   if (np % bm != 0 || ld < np || np % 64 != 0 || n > np) return hipErrorInvalidValue;
+  if (bias != nullptr && !c_f32) return hipErrorInvalidValue;
   switch (e) {
     case Elem::F32:
-      return launch_e<Elem::F32, true>(bm, P, Q, C, n, np, ld, s);
+      return launch_e<Elem::F32, true>(bm, P, Q, C, bias, n, np, ld, s);
     case Elem::BF16:
-      return c_f32 ? launch_e<Elem::BF16, true>(bm, P, Q, C, n, np, ld, s)
-                   : launch_e<Elem::BF16, false>(bm, P, Q, C, n, np, ld, s);
+      return c_f32 ? launch_e<Elem::BF16, true>(bm, P, Q, C, bias, n, np, ld, s)
+                   : launch_e<Elem::BF16, false>(bm, P, Q, C, bias, n, np, ld, s);
     case Elem::F16:
-      return c_f32 ? launch_e<Elem::F16, true>(bm, P, Q, C, n, np, ld, s)
-                   : launch_e<Elem::F16, false>(bm, P, Q, C, n, np, ld, s);
+      return c_f32 ? launch_e<Elem::F16, true>(bm, P, Q, C, bias, n, np, ld, s)
+                   : launch_e<Elem::F16, false>(bm, P, Q, C, bias, n, np, ld, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,242 @@
+// Exact linear assignment by one workgroup, for the discretisation of
+// Algorithm 1, step 10: M = argmin_{P in Pi} ||P - N||_F, i.e. the
+// permutation sigma maximising sum_i N[i, sigma(i)] (eq. 2), which the paper
+// obtains with the Hungarian method (Sec. 6, complexity paragraph).
+//
+// Method: shortest augmenting paths with row and column potentials (the
+// Hungarian method in its Dijkstra form).  With costs c_ij = -N_ij, dual
+// variables u_i, v_j keep every reduced cost c_ij - u_i - v_j >= 0 and make
+// every matched pair tight.  The start is the dual-feasible partial matching
+// of the row maxima (u_i = min_j c_ij, v = 0): a row keeps its argmax column
+// unless a lower-numbered row took it first.  Each still unmatched row, in
+// increasing order, then grows a shortest-path tree over the columns until it
+// reaches an unmatched column, updates the potentials and flips the path.
+// When the row maxima already form a permutation there is nothing to augment.
+//
+// Columns are dealt to threads round-robin and each thread owns the
+// distance, predecessor and scanned flag of its columns, so one step of the
+// tree growth needs one barrier: every wave posts its (distance, column)
+// minimum, and after the barrier every thread reduces the same posted values
+// to the same winner.  Ties go to the lowest column and all arithmetic is
+// FP64 in a fixed order, so the result does not depend on the thread count.
+#pragma once
+
+#include <limits.h>
+
+#include "fram_internal.h"
+
+namespace fram {
+
+// Bytes of the per-problem arrays u, v, dist (FP64), row_of, col_of, pred
+// (int32), scanned (u8), rounded up to 16.  The unmatched-row list (int32[n])
+// is placed by the caller.
+__host__ __device__ inline size_t lap_array_bytes(int n) {
+  return ((size_t)n * (3 * 8 + 3 * 4 + 1) + 15) / 16 * 16;
+}
+
+struct LapArrays {
+  double* u;
+  double* v;
+  double* dist;
+  int* row_of;
+  int* col_of;
+  int* pred;
+  unsigned char* scanned;
+  int* freel;
+};
+
+__device__ inline LapArrays lap_carve(char* base, int n, int* freel) {
+  LapArrays a;
+  a.u = reinterpret_cast<double*>(base);
+  a.v = a.u + n;
+  a.dist = a.v + n;
+  a.row_of = reinterpret_cast<int*>(a.dist + n);
+  a.col_of = a.row_of + n;
+  a.pred = a.col_of + n;
+  a.scanned = reinterpret_cast<unsigned char*>(a.pred + n);
+  a.freel = freel;
+  return a;
+}
+
+template <int NW>
+struct LapShared {
+  double wd[2][NW];
+  int wj[2][NW];
+  int cnt[NW];
+};
+
+__device__ __forceinline__ void lap_better(double& d, int& j, double od, int oj) {
+  if (od < d || (od == d && oj < j)) {
+    d = od;
+    j = oj;
+  }
+}
+
+// Solves max_sigma sum_i W[i, sigma(i)] for the n x n block of W (leading
+// dimension ld) with the NT threads of the calling workgroup (all must call).
+// sigma: on entry the row argmax (lowest column on ties) when u_init is given,
+// on exit the assignment.  u_init: -max_j W[i, j] in FP64, or null to compute
+// both here.  Returns the number of rows that needed an augmenting path, or
+// -1 (sigma all -1) when W holds values that admit no finite path.
+template <int NT>
+__device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t* sigma,
+                         const double* u_init, LapArrays a, LapShared<NT / 64>& sh) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const double inf = __builtin_inf();
+
+  // ---- duals u_i = min_j c_ij = -max_j W_ij and the row argmax (lowest j)
+  if (u_init != nullptr) {
+    for (int i = tid; i < n; i += NT) a.u[i] = u_init[i];
+  } else {
+    for (int i = wave; i < n; i += NW) {
+      const float* r = W + (size_t)i * ld;
+      float best = -INFINITY;
+      int bi = INT_MAX;
+      for (int j = lane; j < n; j += 64) {
+        const float x = r[j];
+        if (x > best) {
+          best = x;
+          bi = j;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        a.u[i] = -(double)best;
+        sigma[i] = bi < n ? bi : -1;
+      }
+    }
+  }
+  for (int j = tid; j < n; j += NT) {
+    a.v[j] = 0.0;
+    a.row_of[j] = INT_MAX;
+  }
+  __syncthreads();
+  // ---- keep tight argmax columns; a column goes to its lowest claiming row
+  for (int i = tid; i < n; i += NT) {
+    const int j = sigma[i];
+    if (j >= 0 && j < n && (-(double)W[(size_t)i * ld + j]) - a.u[i] - a.v[j] == 0.0)
+      atomicMin(&a.row_of[j], i);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    const int j = sigma[i];
+    a.col_of[i] = (j >= 0 && j < n && a.row_of[j] == i) ? j : -1;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NT)
+    if (a.row_of[j] == INT_MAX) a.row_of[j] = -1;
+
+  // ---- unmatched rows in increasing order (ordered compaction)
+  int nfree = 0;
+  for (int base = 0; base < n; base += NT) {
+    const int i = base + tid;
+    const bool f = i < n && a.col_of[i] == -1;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) sh.cnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = nfree;
+    for (int w = 0; w < wave; ++w) off += sh.cnt[w];
+    if (f) a.freel[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    for (int w = 0; w < NW; ++w) nfree += sh.cnt[w];
+    __syncthreads();
+  }
+
+  // ---- one shortest augmenting path per unmatched row
+  int fail = 0;
+  int par = 0;
+  for (int k = 0; k < nfree; ++k) {
+    const int i0 = a.freel[k];
+    const double ui0 = a.u[i0];
+    const float* r0 = W + (size_t)i0 * ld;
+    for (int j = tid; j < n; j += NT) {
+      a.dist[j] = (-(double)r0[j] - ui0) - a.v[j];
+      a.pred[j] = i0;
+      a.scanned[j] = 0;
+    }
+    int jend = -1;
+    double D = 0.0;
+    while (true) {
+      // Closest unscanned column: each thread scans its own columns.  The
+      // posted minima are double-buffered, so one barrier per step suffices.
+      double bd = inf;
+      int bj = INT_MAX;
+      for (int j = tid; j < n; j += NT)
+        if (!a.scanned[j] && a.dist[j] < bd) {
+          bd = a.dist[j];
+          bj = j;
+        }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) lap_better(bd, bj, __shfl_xor(bd, o), __shfl_xor(bj, o));
+      if (lane == 0) {
+        sh.wd[par][wave] = bd;
+        sh.wj[par][wave] = bj;
+      }
+      __syncthreads();
+      bd = sh.wd[par][0];
+      bj = sh.wj[par][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) lap_better(bd, bj, sh.wd[par][w], sh.wj[par][w]);
+      par ^= 1;
+      if (bj == INT_MAX) {  // no finite distance left
+        fail = 1;
+        break;
+      }
+      if (bj % NT == tid) a.scanned[bj] = 1;
+      const int i = a.row_of[bj];
+      if (i == -1) {
+        jend = bj;
+        D = bd;
+        break;
+      }
+      // Relax the unscanned columns through row i (matched to column bj).
+      const double ui = a.u[i];
+      const float* ri = W + (size_t)i * ld;
+      for (int j = tid; j < n; j += NT) {
+        if (a.scanned[j]) continue;
+        const double nd = ((bd + (-(double)ri[j])) - ui) - a.v[j];
+        if (nd < a.dist[j]) {
+          a.dist[j] = nd;
+          a.pred[j] = i;
+        }
+      }
+    }
+    if (fail) break;
+    // Potentials: reduced costs stay >= 0 and the path becomes tight.  Every
+    // scanned column other than jend is matched to a distinct row != i0.
+    for (int j = tid; j < n; j += NT) {
+      if (!a.scanned[j] || j == jend) continue;
+      a.v[j] += a.dist[j] - D;
+      a.u[a.row_of[j]] += D - a.dist[j];
+    }
+    if (tid == 0) a.u[i0] += D;
+    __syncthreads();
+    if (tid == 0) {  // flip the path
+      int j = jend;
+      while (true) {
+        const int i = a.pred[j];
+        const int jprev = a.col_of[i];
+        a.row_of[j] = i;
+        a.col_of[i] = j;
+        if (i == i0) break;
+        j = jprev;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NT) sigma[i] = fail ? -1 : a.col_of[i];
+  __syncthreads();
+  return fail ? -1 : nfree;
+}
+
+}  // namespace fram

@@ -109,6 +109,54 @@ __global__ __launch_bounds__(kT) void cast_scaled_kernel(const double* __restric
   }
 }
 
+// ---------------------------------------------------------------- node term
+__global__ __launch_bounds__(kT) void absmax_partial_kernel(const double* __restrict__ K,
+                                                            size_t nn, double* part) {
+  __shared__ double sh[kT];
+  double m = 0.0;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < nn; t += (size_t)gridDim.x * kT)
+    m = fmax(m, fabs(K[t]));
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kT) void absmax_final_kernel(const double* part, int nblocks,
+                                                          DevState* st) {
+  __shared__ double sh[kT];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kT) m = fmax(m, part[b]);
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) st->maxK = m;
+}
+
+// X's node term on the scale of the edge term A N B / (maxA maxB): any
+// positive common factor of both terms leaves SDSN's result unchanged
+// (Alg. 2 divides by max X), so this equals the paper's c-scaling.
+__global__ __launch_bounds__(kT) void node_term_kernel(const double* __restrict__ K, int n,
+                                                       double w, float* __restrict__ dst, int np,
+                                                       const DevState* st) {
+  const double a = st->maxA, b = st->maxB, mk = st->maxK;
+  const double sc = (a > 0.0 && b > 0.0) ? w / (a * b) : (mk > 0.0 ? w / mk : 0.0);
+  const size_t total = (size_t)np * np;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+    const int i = (int)(t / np), j = (int)(t % np);
+    dst[t] = (i < n && j < n) ? (float)(sc * K[(size_t)i * n + j]) : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kT) void node_objective_kernel(const double* __restrict__ K,
+                                                            const int32_t* __restrict__ sigma,
+                                                            int n, double w, DevState* st) {
+  __shared__ double sh[kT];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += kT) {
+    const int j = sigma[k];
+    acc += (j >= 0 && j < n) ? K[(size_t)k * n + j] : __builtin_nan("");
+  }
+  acc = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) st->objective += 2.0 * w * acc;
+}
+
 template <Elem E>
 __global__ __launch_bounds__(kT) void cast_f32_kernel(const float* __restrict__ src, int n,
                                                       typename Conv<E>::T* __restrict__ dst,
@@ -203,7 +251,8 @@ __global__ __launch_bounds__(kT) void validate_kernel(const double* __restrict__
 
 // ------------------------------------------------------------------ discretise
 __global__ __launch_bounds__(kT) void row_argmax_kernel(const float* __restrict__ N, int n,
-                                                        int np, int32_t* __restrict__ sigma) {
+                                                        int np, int32_t* __restrict__ sigma,
+                                                        double* __restrict__ u) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -226,7 +275,10 @@ __global__ __launch_bounds__(kT) void row_argmax_kernel(const float* __restrict_
       bi = oi;
     }
   }
-  if (lane == 0) sigma[row] = bi < n ? bi : 0;
+  if (lane == 0) {
+    sigma[row] = bi < n ? bi : 0;
+    if (u != nullptr) u[row] = -(double)best;
+  }
 }
 
 __global__ __launch_bounds__(1024) void argmax_track_kernel(const int32_t* __restrict__ cur,
@@ -263,10 +315,20 @@ __global__ __launch_bounds__(kT) void objective_kernel(const double* __restrict_
                                                        double* part) {
   __shared__ double sh[kT];
   double acc = 0.0;
+  // An index outside [0, n) (a failed assignment) makes the sum NaN instead
+  // of being read.
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int sk = sigma[k];
+    if (sk < 0 || sk >= n) {
+      acc = __builtin_nan("");
+      continue;
+    }
     const double* ar = A + (size_t)k * n;
-    const double* br = B + (size_t)sigma[k] * n;
-    for (int l = threadIdx.x; l < n; l += kT) acc += ar[l] * br[sigma[l]];
+    const double* br = B + (size_t)sk * n;
+    for (int l = threadIdx.x; l < n; l += kT) {
+      const int sl = sigma[l];
+      acc += (sl >= 0 && sl < n) ? ar[l] * br[sl] : __builtin_nan("");
+    }
   }
   acc = block_sum_256(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -388,9 +450,10 @@ hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s) {
+hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s,
+                             double* u) {
   const int rows_per_block = kT / 64;
-  row_argmax_kernel<<<(n + rows_per_block - 1) / rows_per_block, kT, 0, s>>>(N, n, np, sigma);
+  row_argmax_kernel<<<(n + rows_per_block - 1) / rows_per_block, kT, 0, s>>>(N, n, np, sigma, u);
   return hipGetLastError();
 }
 
@@ -405,6 +468,20 @@ hipError_t launch_objective(const double* A, const double* B, const int32_t* sig
                             double* part, int nblocks, DevState* st, hipStream_t s) {
   objective_kernel<<<nblocks, kT, 0, s>>>(A, B, sigma, n, part);
   objective_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_term(const double* K, int n, double w, float* dst, int np, double* part,
+                            int nblocks, DevState* st, hipStream_t s) {
+  absmax_partial_kernel<<<nblocks, kT, 0, s>>>(K, (size_t)n * n, part);
+  absmax_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  node_term_kernel<<<grid_for((size_t)np * np), kT, 0, s>>>(K, n, w, dst, np, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_objective(const double* K, const int32_t* sigma, int n, double w,
+                                 DevState* st, hipStream_t s) {
+  node_objective_kernel<<<1, kT, 0, s>>>(K, sigma, n, w, st);
   return hipGetLastError();
 }
 

@@ -37,10 +37,18 @@ struct fram_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profiling pair
   std::string err;
   fram_stats last{};
-  std::vector<float> hostN;  // staging for the host assignment fallback
   int fit_bm = 0, fit_np = 0, fit_ok = 0;  // cached on-chip SDSN feasibility
   unsigned long long launches = 0;         // on-chip launches (barrier epochs)
   unsigned long long* flags = nullptr;     // grid-barrier flags, zeroed once, own allocation
+  // Asynchronous launch timing (profile = 2): event pairs recorded around
+  // launches and read once the stream has passed them.
+  struct Timing {
+    hipEvent_t a, b;
+    double* acc;
+  };
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<Timing> pending;
 };
 
 namespace {
@@ -62,16 +70,16 @@ int choose_tile(int n, int requested) {
 struct Layout {
   int bm = 64, np = 64, nb = 1;
   Elem e = Elem::F32;
-  size_t A64 = 0, B64 = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
+  size_t A64 = 0, B64 = 0, K64 = 0, Kp = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
   size_t rowp[2] = {0, 0}, colp[2] = {0, 0}, tot[2] = {0, 0}, tmax[2] = {0, 0};
-  size_t upd = 0, mx = 0, obj = 0, sigma = 0, sigprev = 0, state = 0;
+  size_t upd = 0, mx = 0, obj = 0, sigma = 0, sigprev = 0, lap = 0, state = 0;
   int nupd = 1, nmax = 1, nobj = 1;
   size_t total = 0;
 };
 
 enum class Use { Solve, SolveDev, Sdsn, Gradient };
 
-Layout plan(int n, Elem e, int tile, Use use) {
+Layout plan(int n, Elem e, int tile, Use use, bool node = false) {
   Layout L;
   L.e = e;
   L.bm = choose_tile(n, tile);
@@ -88,7 +96,9 @@ Layout plan(int n, Elem e, int tile, Use use) {
   if (use == Use::Solve) {
     L.A64 = take((size_t)n * n * 8);
     L.B64 = take((size_t)n * n * 8);
+    if (node) L.K64 = take((size_t)n * n * 8);
   }
+  if (node) L.Kp = take(np2 * 4);
   const bool gemm = use != Use::Sdsn;
   if (gemm) {
     L.Alp = take(np2 * es);
@@ -112,6 +122,7 @@ Layout plan(int n, Elem e, int tile, Use use) {
   L.obj = take((size_t)L.nobj * 8);
   L.sigma = take((size_t)n * 4);
   L.sigprev = take((size_t)n * 4);
+  if (use == Use::Solve || use == Use::SolveDev) L.lap = take(fram::lap_workspace_bytes(n));
   L.state = take(sizeof(DevState));
   L.total = off;
   return L;
@@ -125,7 +136,7 @@ fram_status check_options(const fram_options& o) {
   if (!(o.gamma_tol >= 0.0) || !std::isfinite(o.gamma_tol)) return FRAM_EINVAL;
   if (o.sdsn_max < 1) return FRAM_EINVAL;
   if (!(o.tile == 0 || o.tile == 64 || o.tile == 128 || o.tile == 256)) return FRAM_EINVAL;
-  if (o.profile != 0 && o.profile != 1) return FRAM_EINVAL;
+  if (o.profile < 0 || o.profile > 2) return FRAM_EINVAL;
   if (o.sdsn_mode < 0 || o.sdsn_mode > 2) return FRAM_EINVAL;
   if (o.stable_iters < 0) return FRAM_EINVAL;
   return FRAM_OK;
@@ -218,20 +229,58 @@ fram_status read_state(fram_ctx* c, DevState* dst, hipStream_t s) {
   return FRAM_OK;
 }
 
-// Profiling: when enabled, each timed launch is bracketed by two events on
-// its stream and waited for, so the elapsed time is that launch alone.
+// Profiling.  mode 1: each timed launch is bracketed by two events on its
+// stream and waited for, so the elapsed time is that launch alone (launches
+// serialised).  mode 2: the events are only recorded; their times are
+// collected by flush_timings once the stream has passed them, so the launches
+// keep their normal overlap and host pacing.
 struct Prof {
-  bool on = false;
+  int mode = 0;
   fram_ctx* c = nullptr;
   hipStream_t s = nullptr;
   float last_ms = 0.0f;
 };
 
+fram_status take_events(fram_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+  while (c->evpool.size() < c->evused + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->evpool.push_back(e);
+  }
+  *a = c->evpool[c->evused++];
+  *b = c->evpool[c->evused++];
+  return FRAM_OK;
+}
+
+// Adds the elapsed time of every pending event pair to its counter.
+fram_status flush_timings(fram_ctx* c) {
+  for (const auto& t : c->pending) {
+    HIPCHK(hipEventSynchronize(t.b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+    if (t.acc) *t.acc += ms;
+  }
+  c->pending.clear();
+  c->evused = 0;
+  return FRAM_OK;
+}
+
 template <typename F>
 fram_status timed(Prof& p, double* acc, int* cnt, F&& launch) {
   fram_ctx* c = p.c;
-  if (!p.on) {
+  if (p.mode == 0) {
     HIPCHK(launch());
+    return FRAM_OK;
+  }
+  if (p.mode == 2) {
+    hipEvent_t a, b;
+    fram_status r = take_events(c, &a, &b);
+    if (r != FRAM_OK) return r;
+    HIPCHK(hipEventRecord(a, p.s));
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(b, p.s));
+    c->pending.push_back({a, b, acc});
+    if (cnt) *cnt += 1;
     return FRAM_OK;
   }
   HIPCHK(hipEventRecord(c->ev0, p.s));
@@ -253,10 +302,10 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
   int k = 1;
   const int last = o.sdsn_max + 1;  // pass index that only evaluates gamma
   int chunk = std::max(2, first_chunk);
-  if (o.profile) {
+  if (o.profile == 1) {
     // One pass at a time; the launch that only finds gamma <= gamma_tol is
     // not counted as a pass.
-    Prof p{true, c, s, 0.0f};
+    Prof p{1, c, s, 0.0f};
     for (int kk = 1; kk <= last; ++kk) {
       fram_status r = timed(p, nullptr, nullptr, [&] {
         return fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
@@ -272,12 +321,19 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
     }
     k = last + 1;
   }
-  while (!o.profile) {
+  while (o.profile != 1) {
     const int end = std::min(last, k + chunk - 1);
-    for (int kk = k; kk <= end; ++kk)
-      HIPCHK(fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
-                                    partials(c, L, kk & 1), st, kk, o.sdsn_max, theta,
-                                    o.gamma_tol, s));
+    Prof p{o.profile, c, s, 0.0f};
+    fram_status r0 = timed(p, &stt->ms_sdsn, nullptr, [&] {
+      for (int kk = k; kk <= end; ++kk) {
+        const hipError_t e = fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
+                                                    partials(c, L, kk & 1), st, kk, o.sdsn_max,
+                                                    theta, o.gamma_tol, s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    });
+    if (r0 != FRAM_OK) return r0;
     k = end + 1;
     fram_status r = read_state(c, st, s);
     if (r != FRAM_OK) return r;
@@ -329,7 +385,11 @@ fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool
   return FRAM_OK;
 }
 
-constexpr int kSpinLimit = 1 << 25;
+// Bound on one grid-barrier wait of the on-chip SDSN, in polls (each a
+// relaxed load of a flag plus a short sleep, about a microsecond): about a
+// second, far above a pass's few microseconds, so a launch whose workgroups
+// cannot all meet (they are not co-resident) ends quickly with an error.
+constexpr int kSpinLimit = 1 << 20;
 
 // One on-chip projection: D = SDSN(src) with every pass in one cooperative
 // launch; optionally writes D to dst (ld np) and/or applies the N update.
@@ -361,36 +421,43 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   return FRAM_OK;
 }
 
-fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double* dA,
-                              const double* dB, float* N, int32_t* dsig, DevState* st,
-                              hipStream_t s, int32_t* perm, double* obj, int* host_lap) {
-  HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s));
-  HIPCHK(hipMemcpyAsync(perm, dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+bool is_permutation(const int32_t* p, int n) {
   std::vector<char> seen(n, 0);
-  bool is_perm = true;
   for (int i = 0; i < n; ++i) {
-    const int j = perm[i];
-    if (j < 0 || j >= n || seen[j]) {
-      is_perm = false;
-      break;
-    }
+    const int j = p[i];
+    if (j < 0 || j >= n || seen[j]) return false;
     seen[j] = 1;
   }
-  *host_lap = 0;
-  if (!is_perm) {
-    // Row maxima collide: exact assignment on the host, warm-started from them.
-    c->hostN.resize((size_t)n * L.np);
-    HIPCHK(hipMemcpyAsync(c->hostN.data(), N, (size_t)n * L.np * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    std::vector<int32_t> init(perm, perm + n);
-    fram::host_lap_max(c->hostN.data(), n, L.np, init.data(), perm);
-    HIPCHK(hipMemcpyAsync(dsig, perm, (size_t)n * 4, hipMemcpyHostToDevice, s));
-    *host_lap = 1;
-  }
+  return true;
+}
+
+// Optional node term of eq. (1) / eq. (3): X gains w K (K n x n FP64, device).
+struct NodeTerm {
+  const double* K = nullptr;
+  double w = 0.0;
+};
+
+fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double* dA,
+                              const double* dB, const NodeTerm& nt, float* N, int32_t* dsig,
+                              DevState* st, hipStream_t s, int32_t* perm, double* obj,
+                              int* lap_paths) {
+  // Row argmax of N with the starting duals, then the exact assignment on the
+  // device (nothing to augment when the argmax is a permutation).
+  char* lws = at<char>(c, L.lap);
+  double* u = reinterpret_cast<double*>(lws);
+  HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s, u));
+  fram::LapProblem lp{N, n, L.np, dsig, lws, u, 1, &st->lap_paths};
+  HIPCHK(fram::launch_lap(&lp, nullptr, 1, n, s));
   HIPCHK(fram::launch_objective(dA, dB, dsig, n, at<double>(c, L.obj), L.nobj, st, s));
+  if (nt.K != nullptr) HIPCHK(fram::launch_node_objective(nt.K, dsig, n, nt.w, st, s));
+  HIPCHK(hipMemcpyAsync(perm, dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
   fram_status r = read_state(c, st, s);
   if (r != FRAM_OK) return r;
+  *lap_paths = c->hst->lap_paths;
+  if (!is_permutation(perm, n)) {
+    c->err = "the assignment of N failed (non-finite entries)";
+    return FRAM_ENUMERIC;
+  }
   *obj = c->hst->objective;
   if (!std::isfinite(*obj)) {
     c->err = "non-finite objective";
@@ -400,10 +467,10 @@ fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double*
 }
 
 // Algorithm 1 on device inputs dA, dB (n x n FP64, ld n).
-fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const double* dB, int n,
-                      double theta, int iters, double tol, const fram_options& o,
-                      bool validate_dev, hipStream_t s, int32_t* perm, double* obj,
-                      fram_stats* stt) {
+fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const double* dB,
+                      const NodeTerm& nt, int n, double theta, int iters, double tol,
+                      const fram_options& o, bool validate_dev, hipStream_t s, int32_t* perm,
+                      double* obj, fram_stats* stt) {
   const Elem e = L.e;
   const size_t np2 = (size_t)L.np * L.np;
   DevState* st = at<DevState>(c, L.state);
@@ -415,8 +482,20 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   float* X = at<float>(c, L.X);
   int32_t* dsig = at<int32_t>(c, L.sigma);
 
+  c->pending.clear();
+  c->evused = 0;
   HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
   if (validate_dev) {
+    if (nt.K != nullptr) {  // K may be signed and asymmetric; only finiteness counts
+      HIPCHK(fram::launch_validate(nt.K, n, st, s));
+      fram_status r = read_state(c, st, s);
+      if (r != FRAM_OK) return r;
+      if (c->hst->invalid & 1) {
+        c->err = "device node similarities are non-finite";
+        return FRAM_EINVAL;
+      }
+      HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
+    }
     HIPCHK(fram::launch_validate(dA, n, st, s));
     HIPCHK(fram::launch_validate(dB, n, st, s));
     fram_status r = read_state(c, st, s);
@@ -431,6 +510,11 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   HIPCHK(fram::launch_maxes(dA, dB, n, at<double>(c, L.mx), L.nmax, st, s));
   HIPCHK(fram::launch_cast_scaled(e, dA, n, Alp, L.np, st, 0, s));
   HIPCHK(fram::launch_cast_scaled(e, dB, n, Blp, L.np, st, 1, s));
+  float* Kp = nullptr;
+  if (nt.K != nullptr) {
+    Kp = at<float>(c, L.Kp);
+    HIPCHK(fram::launch_node_term(nt.K, n, nt.w, Kp, L.np, at<double>(c, L.mx), L.nmax, st, s));
+  }
   // Algorithm 1, step 1: N^(0) = 0.
   HIPCHK(fram::launch_zero(N, np2 * 4, s));
   if (e != Elem::F32) HIPCHK(fram::launch_zero(Nlp, np2 * fram::elem_size(e), s));
@@ -441,7 +525,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   int est = 8;
   int stable = 0;
   bool prev_perm = false;
-  Prof prof{o.profile != 0, c, s, 0.0f};
+  Prof prof{o.profile, c, s, 0.0f};
   bool onchip = false;
   {
     fram_status q = use_onchip(c, L, o, &onchip);
@@ -454,7 +538,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     });
     if (r != FRAM_OK) return r;
     r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
-      return fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s);
+      return fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s, Kp);
     });
     if (r != FRAM_OK) return r;
     if (onchip) {
@@ -469,11 +553,6 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
         return fram::launch_delta_final(at<double>(c, L.upd), L.nb * L.nb, st, s);
       });
       if (r != FRAM_OK) return r;
-      if (prof.on) {
-        r = read_state(c, st, s);
-        if (r != FRAM_OK) return r;
-        stt->sdsn_launches += c->hst->passes;
-      }
     } else {
       r = timed(prof, &stt->ms_stats, nullptr, [&] {
         return fram::launch_tile_stats(L.bm, X, L.np, nullptr, n, L.np, partials(c, L, 0), st,
@@ -532,8 +611,10 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     }
   }
   if (it > iters) it = iters;
-  int host_lap = 0;
-  fram_status r = finish_discretise(c, L, n, dA, dB, N, dsig, st, s, perm, obj, &host_lap);
+  int lap_paths = 0;
+  fram_status r = finish_discretise(c, L, n, dA, dB, nt, N, dsig, st, s, perm, obj, &lap_paths);
+  if (r != FRAM_OK) return r;
+  r = flush_timings(c);
   if (r != FRAM_OK) return r;
   if (onchip) {
     // finish_discretise left the device state in c->hst.
@@ -551,13 +632,15 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       return FRAM_ENUMERIC;
     }
   }
+  if (o.profile != 0 && onchip) stt->sdsn_launches = it;  // one launch per projection
+  if (o.profile == 2 && !onchip) stt->sdsn_launches = total_passes;
   stt->outer_iters = it;
   stt->sdsn_passes = total_passes;
   stt->sdsn_passes_last = last_passes;
   stt->sdsn_passes_max = max_passes_seen;
   stt->converged = converged ? 1 : 0;
   stt->sdsn_capped = any_capped ? 1 : 0;
-  stt->host_lap = host_lap;
+  stt->lap_paths = lap_paths;
   stt->gemm_tile = L.bm;
   stt->delta = delta;
   stt->gamma = gamma;
@@ -575,17 +658,17 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-fram_status solve_host_impl(fram_ctx* c, const double* A, const double* B, int n, double theta,
-                            int iters, double tol, const fram_options& o, int32_t* perm,
-                            double* obj, fram_stats* stt) {
+fram_status solve_host_impl(fram_ctx* c, const double* A, const double* B, const double* K,
+                            double w, int n, double theta, int iters, double tol,
+                            const fram_options& o, int32_t* perm, double* obj, fram_stats* stt) {
   const double t0 = now_ms();
   if (n == 1) {
     perm[0] = 0;
-    *obj = A[0] * B[0];
+    *obj = A[0] * B[0] + (K ? 2.0 * w * K[0] : 0.0);
     stt->ms_total = now_ms() - t0;
     return FRAM_OK;
   }
-  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::Solve);
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::Solve, K != nullptr);
   if (c->budget != 0 && L.total > c->budget) {
     c->err = "workspace exceeds the HBM budget";
     return FRAM_ENOMEM;
@@ -599,8 +682,54 @@ fram_status solve_host_impl(fram_ctx* c, const double* A, const double* B, int n
   double* dB = at<double>(c, L.B64);
   HIPCHK(hipMemcpyAsync(dA, A, (size_t)n * n * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dB, B, (size_t)n * n * 8, hipMemcpyHostToDevice, s));
-  r = run_solve(c, L, dA, dB, n, theta, iters, tol, o, false, s, perm, obj, stt);
+  NodeTerm nt;
+  if (K != nullptr) {
+    nt.K = at<double>(c, L.K64);
+    nt.w = w;
+    HIPCHK(hipMemcpyAsync(at<double>(c, L.K64), K, (size_t)n * n * 8, hipMemcpyHostToDevice, s));
+  }
+  r = run_solve(c, L, dA, dB, nt, n, theta, iters, tol, o, false, s, perm, obj, stt);
   stt->ms_total = now_ms() - t0;
+  return r;
+}
+
+// Device-input solve shared by fram_solve_dev and fram_solve_attr_dev.
+fram_status solve_dev_impl(fram_ctx* c, const double* dA, const double* dB, const double* dK,
+                           double w, int n, double lambda, int iters, double tol,
+                           const fram_options& o, int32_t* perm_out, double* objective_out,
+                           fram_stats* stats, void* stream) {
+  const double t0 = now_ms();
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::SolveDev, dK != nullptr);
+  if (c->budget != 0 && L.total > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, L.total);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  fram_stats st{};
+  if (n == 1) {
+    double a = 0, b = 0, k = 0;
+    HIPCHK(hipMemcpyAsync(&a, dA, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&b, dB, 8, hipMemcpyDeviceToHost, s));
+    if (dK) HIPCHK(hipMemcpyAsync(&k, dK, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(k) && a >= 0 && b >= 0))
+      return FRAM_EINVAL;
+    perm_out[0] = 0;
+    *objective_out = a * b + 2.0 * w * k;
+  } else {
+    NodeTerm nt;
+    nt.K = dK;
+    nt.w = dK ? w : 0.0;
+    r = run_solve(c, L, dA, dB, nt, n, lambda, iters, tol, o, true, s, perm_out, objective_out,
+                  &st);
+  }
+  st.ms_total = now_ms() - t0;
+  c->last = st;
+  if (stats) *stats = st;
   return r;
 }
 
@@ -665,7 +794,8 @@ fram_status fram_solve_ex(fram_ctx* c, const double* A, const double* B, int n, 
     return r;
   }
   fram_stats st{};
-  r = solve_host_impl(c, A, B, n, lambda, iters, tol, o, perm_out, objective_out, &st);
+  r = solve_host_impl(c, A, B, nullptr, 0.0, n, lambda, iters, tol, o, perm_out, objective_out,
+                      &st);
   c->last = st;
   if (stats) *stats = st;
   return r;
@@ -689,33 +819,50 @@ fram_status fram_solve_dev(fram_ctx* c, const double* dA, const double* dB, int 
     c->err = "invalid argument";
     return r;
   }
-  const double t0 = now_ms();
-  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::SolveDev);
-  if (c->budget != 0 && L.total > c->budget) {
-    c->err = "workspace exceeds the HBM budget";
-    return FRAM_ENOMEM;
+  return solve_dev_impl(c, dA, dB, nullptr, 0.0, n, lambda, iters, tol, o, perm_out,
+                        objective_out, stats, stream);
+}
+
+fram_status fram_solve_attr_ex(fram_ctx* c, const double* A, const double* B, const double* K,
+                               int n, double node_weight, double lambda, int iters, double tol,
+                               const fram_options* opt, int32_t* perm_out, double* objective_out,
+                               fram_stats* stats) {
+  if (!c || !A || !B || !K || !perm_out || !objective_out) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
+  if (r == FRAM_OK) r = check_graph(A, n);
+  if (r == FRAM_OK) r = check_graph(B, n);
+  if (r == FRAM_OK && !std::isfinite(node_weight)) r = FRAM_EINVAL;
+  for (size_t t = 0; r == FRAM_OK && t < (size_t)n * n; ++t)
+    if (!std::isfinite(K[t])) r = FRAM_EINVAL;
+  if (r != FRAM_OK) {
+    c->err = "invalid argument";
+    return r;
   }
-  r = ensure_device(c);
-  if (r != FRAM_OK) return r;
-  r = ensure_ws(c, L.total);
-  if (r != FRAM_OK) return r;
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   fram_stats st{};
-  if (n == 1) {
-    double a = 0, b = 0;
-    HIPCHK(hipMemcpyAsync(&a, dA, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&b, dB, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (!(std::isfinite(a) && std::isfinite(b) && a >= 0 && b >= 0)) return FRAM_EINVAL;
-    perm_out[0] = 0;
-    *objective_out = a * b;
-  } else {
-    r = run_solve(c, L, dA, dB, n, lambda, iters, tol, o, true, s, perm_out, objective_out, &st);
-  }
-  st.ms_total = now_ms() - t0;
+  r = solve_host_impl(c, A, B, K, node_weight, n, lambda, iters, tol, o, perm_out, objective_out,
+                      &st);
   c->last = st;
   if (stats) *stats = st;
   return r;
+}
+
+fram_status fram_solve_attr_dev(fram_ctx* c, const double* dA, const double* dB,
+                                const double* dK, int n, double node_weight, double lambda,
+                                int iters, double tol, const fram_options* opt, int32_t* perm_out,
+                                double* objective_out, fram_stats* stats, void* stream) {
+  if (!c || !dA || !dB || !dK || !perm_out || !objective_out) return FRAM_EINVAL;
+  fram_options o = opt ? *opt : defaults();
+  fram_status r = check_options(o);
+  if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
+  if (r == FRAM_OK && !std::isfinite(node_weight)) r = FRAM_EINVAL;
+  if (r != FRAM_OK) {
+    c->err = "invalid argument";
+    return r;
+  }
+  return solve_dev_impl(c, dA, dB, dK, node_weight, n, lambda, iters, tol, o, perm_out,
+                        objective_out, stats, stream);
 }
 
 fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, double lambda,
@@ -741,6 +888,8 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   DevState* st = at<DevState>(c, L.state);
   float* X = at<float>(c, L.X);
+  c->pending.clear();
+  c->evused = 0;
   HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
   int passes = 0;
   double gamma = 0.0;
@@ -750,7 +899,7 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   r = use_onchip(c, L, o, &onchip);
   if (r != FRAM_OK) return r;
   if (onchip) {
-    Prof prof{o.profile != 0, c, s, 0.0f};
+    Prof prof{o.profile, c, s, 0.0f};
     r = timed(prof, &stt.ms_sdsn, nullptr, [&] {
       fram_status q = run_sdsn_onchip(c, L, n, dK, ldk, X, nullptr, nullptr, Elem::F32, 0.95, st,
                                       lambda, o, s);
@@ -778,6 +927,9 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   }
   HIPCHK(fram::launch_copy_f32(X, L.np, dX, ldx, n, s));
   HIPCHK(hipStreamSynchronize(s));
+  r = flush_timings(c);
+  if (r != FRAM_OK) return r;
+  if (o.profile == 2) stt.sdsn_launches = onchip ? 1 : passes;
   stt.sdsn_passes = passes;
   stt.sdsn_passes_last = passes;
   stt.sdsn_passes_max = passes;
@@ -953,7 +1105,6 @@ fram_status solve_batched(fram_ctx* c, const std::vector<int>& ids, const double
   a.iters = iters;
   a.sdsn_max = o.sdsn_max;
   a.stable_iters = o.stable_iters;
-  a.objective_only = 0;
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
   const int grid = std::max(1, std::min(m, 3 * cus));
@@ -965,40 +1116,15 @@ fram_status solve_batched(fram_ctx* c, const std::vector<int>& ids, const double
   HIPCHK(hipMemcpyAsync(sig.data(), ar + sig_base, sig_elems * 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
 
-  // Pairs whose row argmax collides: exact assignment on the host, then the
-  // objective of the new permutation on the device.
-  std::vector<int> fix;
-  for (int q = 0; q < m; ++q)
-    if (!res[q].is_perm) fix.push_back(q);
-  if (!fix.empty()) {
-    for (int q : fix) {
-      const int nn = pairs[q].n, np = pairs[q].np;
-      c->hostN.resize((size_t)nn * np);
-      HIPCHK(hipMemcpyAsync(c->hostN.data(), ar + pairs[q].nf, (size_t)nn * np * 4,
-                            hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      int32_t* sq = &sig[(pairs[q].sigma - (long long)sig_base) / 4];
-      std::vector<int32_t> init(sq, sq + nn);
-      fram::host_lap_max(c->hostN.data(), nn, np, init.data(), sq);
-      HIPCHK(hipMemcpyAsync(ar + pairs[q].sigma, sq, (size_t)nn * 4, hipMemcpyHostToDevice, s));
-    }
-    HIPCHK(hipMemcpyAsync(ar + order_off, fix.data(), sizeof(int) * fix.size(),
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(fram::launch_zero(ar + next_off, sizeof(int), s));
-    a.count = (int)fix.size();
-    a.objective_only = 1;
-    HIPCHK(fram::launch_fram_batch(e, a, std::max(1, std::min(a.count, 3 * cus)), s));
-    std::vector<fram::BatchResult> res2(m);
-    HIPCHK(hipMemcpyAsync(res2.data(), ar + res_off, sizeof(fram::BatchResult) * m,
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int q : fix) res[q].objective = res2[q].objective;
-  }
   for (int q = 0; q < m; ++q) {
     const int p = ids[q];
     const int32_t* sq = &sig[(pairs[q].sigma - (long long)sig_base) / 4];
     std::memcpy(perm_out[p], sq, (size_t)pairs[q].n * 4);
     objective_out[p] = res[q].objective;
+    if (!is_permutation(sq, pairs[q].n)) {
+      c->err = "no finite assignment in batched pair " + std::to_string(p);
+      return FRAM_ENUMERIC;
+    }
     if (!std::isfinite(res[q].objective) || !std::isfinite(res[q].delta) ||
         !std::isfinite(res[q].gamma)) {
       c->err = "non-finite value in batched pair " + std::to_string(p);
@@ -1013,7 +1139,7 @@ fram_status solve_batched(fram_ctx* c, const std::vector<int>& ids, const double
       st.sdsn_passes_max = res[q].sdsn_passes_max;
       st.converged = res[q].converged;
       st.sdsn_capped = res[q].sdsn_capped;
-      st.host_lap = res[q].is_perm ? 0 : 1;
+      st.lap_paths = res[q].is_perm ? 0 : res[q].lap_paths;
       st.gemm_tile = 32;
       st.delta = res[q].delta;
       st.gamma = res[q].gamma;
@@ -1065,7 +1191,7 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
   // Pairs too large for one workgroup go through the single-pair path.
   for (int p : single) {
     fram_stats st{};
-    r = solve_host_impl(c, A[p], B[p], n[p], lambda, iters, tol, o, perm_out[p],
+    r = solve_host_impl(c, A[p], B[p], nullptr, 0.0, n[p], lambda, iters, tol, o, perm_out[p],
                         &objective_out[p], &st);
     if (stats) stats[p] = st;
     if (r != FRAM_OK) return r;
@@ -1085,19 +1211,71 @@ fram_status fram_solve_many(fram_ctx* c, int count, const double* const* A,
                             objective_out, nullptr);
 }
 
-fram_status fram_assign(const float* W, int n, int32_t* perm_out) {
-  if (!W || !perm_out || n < 1) return FRAM_EINVAL;
+namespace {
+
+// Workspace of the assignment entry points: the assignment's arrays, then
+// the device state.
+size_t assign_ws_bytes(int n) {
+  return align_up(fram::lap_workspace_bytes(n)) + align_up(sizeof(DevState));
+}
+
+// Device assignment of an n x n FP32 matrix at dW (leading dimension ldw)
+// into dperm on stream s, then a check that the result is a permutation.
+fram_status assign_on_device(fram_ctx* c, const float* dW, int ldw, int n, int32_t* dperm,
+                             hipStream_t s, int32_t* host_perm) {
+  const size_t st_off = align_up(fram::lap_workspace_bytes(n));
+  fram_status r = ensure_ws(c, assign_ws_bytes(n));
+  if (r != FRAM_OK) return r;
+  char* lws = at<char>(c, 0);
+  DevState* st = at<DevState>(c, st_off);
+  double* u = reinterpret_cast<double*>(lws);
+  HIPCHK(fram::launch_zero(st, sizeof(DevState), s));
+  HIPCHK(fram::launch_row_argmax(dW, n, ldw, dperm, s, u));
+  fram::LapProblem lp{dW, n, ldw, dperm, lws, u, 1, &st->lap_paths};
+  HIPCHK(fram::launch_lap(&lp, nullptr, 1, n, s));
+  HIPCHK(hipMemcpyAsync(host_perm, dperm, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  r = read_state(c, st, s);
+  if (r != FRAM_OK) return r;
+  c->last = fram_stats{};
+  c->last.lap_paths = c->hst->lap_paths;
+  if (!is_permutation(host_perm, n)) {
+    c->err = "no finite assignment (non-finite entries)";
+    return FRAM_ENUMERIC;
+  }
+  return FRAM_OK;
+}
+
+}  // namespace
+
+fram_status fram_assign(fram_ctx* c, const float* W, int n, int32_t* perm_out) {
+  if (!c || !W || !perm_out || n < 1) return FRAM_EINVAL;
   for (size_t t = 0; t < (size_t)n * n; ++t)
     if (!std::isfinite(W[t])) return FRAM_EINVAL;
-  std::vector<int32_t> init(n);
-  for (int i = 0; i < n; ++i) {
-    int bi = 0;
-    for (int j = 1; j < n; ++j)
-      if (W[(size_t)i * n + j] > W[(size_t)i * n + bi]) bi = j;
-    init[i] = bi;
+  const size_t wbytes = align_up((size_t)n * n * 4);
+  const size_t base = assign_ws_bytes(n);
+  if (c->budget != 0 && base + wbytes + align_up((size_t)n * 4) > c->budget) {
+    c->err = "workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
   }
-  fram::host_lap_max(W, n, n, init.data(), perm_out);
-  return FRAM_OK;
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, base + wbytes + align_up((size_t)n * 4));
+  if (r != FRAM_OK) return r;
+  hipStream_t s = c->stream;
+  float* dW = at<float>(c, base);
+  int32_t* dp = at<int32_t>(c, base + wbytes);
+  HIPCHK(hipMemcpyAsync(dW, W, (size_t)n * n * 4, hipMemcpyHostToDevice, s));
+  return assign_on_device(c, dW, n, n, dp, s, perm_out);
+}
+
+fram_status fram_assign_dev(fram_ctx* c, const float* dW, int ldw, int n, int32_t* dperm,
+                            void* stream) {
+  if (!c || !dW || !dperm || n < 1 || ldw < n) return FRAM_EINVAL;
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  std::vector<int32_t> host(n);
+  return assign_on_device(c, dW, ldw, n, dperm, s, host.data());
 }
 
 fram_status fram_last_stats(const fram_ctx* c, fram_stats* out) {

@@ -151,12 +151,20 @@ __global__ __launch_bounds__(4 * BM) void sdsn_persistent_kernel(PersistArgs a) 
     // All reads of the previous pass's partials are issued before any wait:
     // the tile totals, then thread (p, r)'s chains p of row r's and column
     // r's partial sums (combined in a fixed order after the barrier below).
+    // The totals decide when every workgroup leaves the loop, so they are
+    // read with agent-scope atomic loads, which never hit a stale cache line
+    // even if a cache's invalidation were missed: all workgroups must see the
+    // same values to take the same decision.
     double part = 0.0;
 #pragma unroll 1
-    for (int u = tid; u < nb * nb; u += NT) part += at_u32(in.tot, (unsigned)u);
+    for (int u = tid; u < nb * nb; u += NT)
+      part += __hip_atomic_load(&at_u32(in.tot, (unsigned)u), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
     float m = -INFINITY;
     if (k == 1)
-      for (int u = tid; u < nb * nb; u += NT) m = fmaxf(m, at_u32(in.tmax, (unsigned)u));
+      for (int u = tid; u < nb * nb; u += NT)
+        m = fmaxf(m, __hip_atomic_load(&at_u32(in.tmax, (unsigned)u), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT));
     {
       const int r = tid % BM, p = tid / BM;
       const unsigned ro = (unsigned)(bm * BM + r), co = (unsigned)(bn * BM + r);

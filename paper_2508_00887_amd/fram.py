@@ -32,7 +32,7 @@ class Stats(ctypes.Structure):
         ("sdsn_passes_max", ctypes.c_int),
         ("converged", ctypes.c_int),
         ("sdsn_capped", ctypes.c_int),
-        ("host_lap", ctypes.c_int),
+        ("lap_paths", ctypes.c_int),
         ("gemm_tile", ctypes.c_int),
         ("delta", ctypes.c_double),
         ("gamma", ctypes.c_double),
@@ -81,11 +81,14 @@ _SIGS = {
     "fram_solve": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P]),
     "fram_solve_ex": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P]),
     "fram_solve_dev": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P, _P]),
+    "fram_solve_attr_ex": (_I, [_P, _P, _P, _P, _I, _D, _D, _I, _D, _P, _P, _P, _P]),
+    "fram_solve_attr_dev": (_I, [_P, _P, _P, _P, _I, _D, _D, _I, _D, _P, _P, _P, _P, _P]),
     "fram_sdsn_project": (_I, [_P, _P, _I, _D, _P]),
     "fram_sdsn_project_ex": (_I, [_P, _P, _I, _D, _P, _P, _P]),
     "fram_sdsn_project_dev": (_I, [_P, _P, _I, _I, _D, _P, _P, _I, _P, _P]),
     "fram_gradient": (_I, [_P, _P, _P, _P, _I, _I, _P]),
-    "fram_assign": (_I, [_P, _I, _P]),
+    "fram_assign": (_I, [_P, _P, _I, _P]),
+    "fram_assign_dev": (_I, [_P, _P, _I, _I, _P, _P]),
     "fram_solve_many": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P]),
     "fram_solve_many_ex": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P, _P, _P]),
     "fram_last_stats": (_I, [_P, _P]),
@@ -176,7 +179,9 @@ def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
              profile=False, sdsn_mode="auto", stable_iters=0) -> Options:
     o = Options()
     o.stable_iters = int(stable_iters)
-    o.profile = 1 if profile else 0
+    # profile: False/0 off, True/1 each launch timed alone, 2 timed without
+    # serialising the launches.
+    o.profile = int(profile)
     o.sdsn_mode = SDSN_MODES[sdsn_mode] if isinstance(sdsn_mode, str) else int(sdsn_mode)
     o.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     o.alpha = alpha
@@ -211,31 +216,47 @@ class Context:
             pass
 
     # ------------------------------------------------------------ FRAM
-    def solve(self, A, B, theta=2.0, iters=100, tol=0.0, **opts):
-        """fram_solve_ex on host arrays; returns (perm, objective, stats dict)."""
+    def solve(self, A, B, theta=2.0, iters=100, tol=0.0, K=None, node_weight=1.0, **opts):
+        """fram_solve_ex (or fram_solve_attr_ex when node similarities K are
+        given) on host arrays; returns (perm, objective, stats dict)."""
         A, B = _f64(A), _f64(B)
         n = A.shape[0]
         perm = np.empty(n, dtype=np.int32)
         obj = ctypes.c_double()
         stats = Stats()
         o = _options(**opts)
-        st = self.lib.fram_solve_ex(self.handle, _ptr(A), _ptr(B), n, theta, iters, tol,
-                                    ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
-                                    ctypes.byref(stats))
-        _check(self.handle, st, "fram_solve_ex")
+        if K is None:
+            st = self.lib.fram_solve_ex(self.handle, _ptr(A), _ptr(B), n, theta, iters, tol,
+                                        ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
+                                        ctypes.byref(stats))
+            _check(self.handle, st, "fram_solve_ex")
+        else:
+            K = _f64(K)
+            st = self.lib.fram_solve_attr_ex(self.handle, _ptr(A), _ptr(B), _ptr(K), n,
+                                             node_weight, theta, iters, tol, ctypes.byref(o),
+                                             _ptr(perm), ctypes.byref(obj), ctypes.byref(stats))
+            _check(self.handle, st, "fram_solve_attr_ex")
         return perm.astype(np.int64), obj.value, stats.as_dict()
 
     def solve_dev(self, dA: int, dB: int, n: int, theta=2.0, iters=100, tol=0.0, stream=0,
-                  **opts):
-        """fram_solve_dev on device pointers (n*n doubles each)."""
+                  dK: int = 0, node_weight=1.0, **opts):
+        """fram_solve_dev (fram_solve_attr_dev with dK) on device pointers
+        (n*n doubles each)."""
         perm = np.empty(n, dtype=np.int32)
         obj = ctypes.c_double()
         stats = Stats()
         o = _options(**opts)
-        st = self.lib.fram_solve_dev(self.handle, dA, dB, n, theta, iters, tol, ctypes.byref(o),
-                                     _ptr(perm), ctypes.byref(obj), ctypes.byref(stats),
-                                     stream or None)
-        _check(self.handle, st, "fram_solve_dev")
+        if not dK:
+            st = self.lib.fram_solve_dev(self.handle, dA, dB, n, theta, iters, tol,
+                                         ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
+                                         ctypes.byref(stats), stream or None)
+            _check(self.handle, st, "fram_solve_dev")
+        else:
+            st = self.lib.fram_solve_attr_dev(self.handle, dA, dB, dK, n, node_weight, theta,
+                                              iters, tol, ctypes.byref(o), _ptr(perm),
+                                              ctypes.byref(obj), ctypes.byref(stats),
+                                              stream or None)
+            _check(self.handle, st, "fram_solve_attr_dev")
         return perm.astype(np.int64), obj.value, stats.as_dict()
 
     def sdsn_project(self, K, theta=2.0, gamma_tol=1e-6, sdsn_max=1000, tile=0,
@@ -271,6 +292,20 @@ class Context:
         _check(self.handle, st, "fram_gradient")
         return X
 
+    def assign(self, W) -> np.ndarray:
+        """fram_assign: exact assignment maximising sum_i W[i, perm[i]] (eq. 2)."""
+        W = _f32(W)
+        n = W.shape[0]
+        perm = np.empty(n, dtype=np.int32)
+        _check(self.handle, self.lib.fram_assign(self.handle, _ptr(W), n, _ptr(perm)),
+               "fram_assign")
+        return perm.astype(np.int64)
+
+    def assign_dev(self, dW: int, ldw: int, n: int, dperm: int, stream=0):
+        """fram_assign_dev on device pointers (dperm: n int32)."""
+        _check(self.handle, self.lib.fram_assign_dev(self.handle, dW, ldw, n, dperm, stream),
+               "fram_assign_dev")
+
     def solve_many(self, As, Bs, theta=2.0, iters=100, tol=0.0, **opts):
         """fram_solve_many_ex; returns (list of perms, objectives array, list of stats)."""
         As = [_f64(a) for a in As]
@@ -295,12 +330,4 @@ class Context:
         return s.as_dict()
 
 
-def fram_assign(W) -> np.ndarray:
-    """Exact linear assignment maximising sum_i W[i, perm[i]] (eq. 2), host side."""
-    W = _f32(W)
-    n = W.shape[0]
-    perm = np.empty(n, dtype=np.int32)
-    st = load_library().fram_assign(_ptr(W), n, _ptr(perm))
-    if st != FRAM_OK:
-        raise FramError(st, "fram_assign", fram_status_str(st))
-    return perm.astype(np.int64)
+
