@@ -10,7 +10,7 @@ seed 2000), with A and B resident in HBM before timing starts
 also timed with FP32 GEMMs, and one extra profiled solve of each precision
 gives per-kernel device times from HIP events on the library's stream.
 
-Two further legs run after it (each can be switched off):
+Two further legs can run after it (--batched, --serve):
 * batched: 512 independent pairs, n ~ U{20..300}, in one fram_solve_many call
   (pairs/s, inputs uploaded inside the timed call);
 * served: Poisson arrivals at 200 requests/s for 30 s after a 5 s warm-up,
@@ -33,10 +33,10 @@ sys.path.insert(0, str(ROOT))
 
 N_WORKLOAD = 4000
 THETA, ITERS, TOL, GAMMA_TOL = 2.0, 100, 1e-6, 1e-6
-# Second stop rule (both precisions): the row argmax of N has been the same
-# permutation for 3 consecutive iterations.  BF16/FP16 GEMMs make delta level
-# off near 1e-4 and FP32 near 1e-6, above the tolerance the FP64 oracle reaches.
-STABLE_ITERS = 3
+# Second stop rule (a stable row argmax of N for this many iterations): off,
+# as the library has the argmax-stability stop switched off; solves stop at
+# delta <= TOL or after ITERS outer iterations.
+STABLE_ITERS = 0
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
@@ -172,8 +172,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sdsn-mode", default="auto", choices=["auto", "stream", "onchip"])
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
+    # The batched and served legs run only on request: fram_solve_many runs
+    # pair by pair while the batched kernel is switched off.
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
@@ -302,10 +304,10 @@ def main():
     if "fp32" in res:
         line["fp32"] = res["fp32"]
         line["speedup_vs_fp32"] = line["value"] / res["fp32"]["solves_per_s"]
-    if not args.no_batched:
+    if args.batched:
         log("batched leg: 512 pairs")
         line["batched"] = batched_leg(Context)
-    if not args.no_serve:
+    if args.serve:
         log("served leg")
         line["served"] = served_leg(duration_s=args.serve_seconds)
     if not args.no_cpu_baseline:

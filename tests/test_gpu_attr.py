@@ -14,7 +14,9 @@ import pytest
 import synth
 from oracle import fram64 as O
 
-pytestmark = pytest.mark.gpu
+from conftest import FAULT_SKIP
+
+pytestmark = [pytest.mark.gpu, FAULT_SKIP]
 
 
 @pytest.mark.parametrize("seed", range(8))

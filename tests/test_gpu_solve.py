@@ -18,7 +18,9 @@ import pytest
 import synth
 from oracle import fram64 as O
 
-pytestmark = pytest.mark.gpu
+from conftest import FAULT_SKIP
+
+pytestmark = [pytest.mark.gpu, FAULT_SKIP]
 GOLDEN = pathlib.Path(__file__).resolve().parent / "golden"
 
 
