@@ -18,8 +18,6 @@ struct DevState {
   int total_passes;  // passes summed over projections (on-chip SDSN path)
   int max_passes;    // largest pass count of one projection (on-chip SDSN path)
   int capped;        // some projection hit the pass cap (on-chip SDSN path)
-  int arg_perm;      // row argmax of N is a permutation (argmax tracking)
-  int arg_same;      // ... and equals the previous iteration's argmax
   int lap_paths;     // augmenting paths of the final assignment (-1: failed)
   double gamma;      // gamma of the last SDSN output
   double delta;      // delta of the last outer update
@@ -181,13 +179,6 @@ hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s);
 // also u[i] = -max_j N[i, j] in FP64 (the assignment's starting duals).
 hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipStream_t s,
                              double* u = nullptr);
-
-// Argmax tracking for the stability stop: cur (written by row_argmax) is
-// checked for being a permutation and compared with prev; then prev = cur.
-// Sets st->arg_perm and st->arg_same.  n <= kTrackMaxN.
-constexpr int kTrackMaxN = 16384;
-hipError_t launch_argmax_track(const int32_t* cur, int32_t* prev, int n, DevState* st,
-                               hipStream_t s);
 
 // st->objective = sum_{k,l} A_kl B_{sigma(k) sigma(l)} in FP64.
 hipError_t launch_objective(const double* A, const double* B, const int32_t* sigma, int n,

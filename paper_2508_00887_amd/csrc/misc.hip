@@ -281,33 +281,6 @@ __global__ __launch_bounds__(kT) void row_argmax_kernel(const float* __restrict_
   }
 }
 
-__global__ __launch_bounds__(1024) void argmax_track_kernel(const int32_t* __restrict__ cur,
-                                                            int32_t* __restrict__ prev, int n,
-                                                            DevState* st) {
-  __shared__ int hits[kTrackMaxN];
-  __shared__ int s_perm, s_same;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) hits[j] = 0;
-  if (threadIdx.x == 0) {
-    s_perm = 1;
-    s_same = 1;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int j = cur[i];
-    if (j >= 0 && j < n) atomicAdd(&hits[j], 1);
-    if (j != prev[i]) s_same = 0;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < n; j += blockDim.x)
-    if (hits[j] != 1) s_perm = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) prev[i] = cur[i];
-  if (threadIdx.x == 0) {
-    st->arg_perm = s_perm;
-    st->arg_same = s_same;
-  }
-}
-
 // ------------------------------------------------------------------ objective
 __global__ __launch_bounds__(kT) void objective_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ B,
@@ -454,13 +427,6 @@ hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipS
                              double* u) {
   const int rows_per_block = kT / 64;
   row_argmax_kernel<<<(n + rows_per_block - 1) / rows_per_block, kT, 0, s>>>(N, n, np, sigma, u);
-  return hipGetLastError();
-}
-
-hipError_t launch_argmax_track(const int32_t* cur, int32_t* prev, int n, DevState* st,
-                               hipStream_t s) {
-  if (n > kTrackMaxN) return hipErrorInvalidValue;
-  argmax_track_kernel<<<1, 1024, 0, s>>>(cur, prev, n, st);
   return hipGetLastError();
 }
 

@@ -49,6 +49,9 @@ struct fram_ctx {
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<Timing> pending;
+  // Argmax-stability stop: the row argmax of N of this and of the previous
+  // outer iteration (host copies).
+  std::vector<int32_t> arg_cur, arg_prev;
 };
 
 namespace {
@@ -72,7 +75,7 @@ struct Layout {
   Elem e = Elem::F32;
   size_t A64 = 0, B64 = 0, K64 = 0, Kp = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
   size_t rowp[2] = {0, 0}, colp[2] = {0, 0}, tot[2] = {0, 0}, tmax[2] = {0, 0};
-  size_t upd = 0, mx = 0, obj = 0, sigma = 0, sigprev = 0, lap = 0, state = 0;
+  size_t upd = 0, mx = 0, obj = 0, sigma = 0, lap = 0, state = 0;
   int nupd = 1, nmax = 1, nobj = 1;
   size_t total = 0;
 };
@@ -121,7 +124,6 @@ Layout plan(int n, Elem e, int tile, Use use, bool node = false) {
   L.mx = take((size_t)L.nmax * 16);
   L.obj = take((size_t)L.nobj * 8);
   L.sigma = take((size_t)n * 4);
-  L.sigprev = take((size_t)n * 4);
   if (use == Use::Solve || use == Use::SolveDev) L.lap = take(fram::lap_workspace_bytes(n));
   L.state = take(sizeof(DevState));
   L.total = off;
@@ -133,11 +135,10 @@ bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP
 // Paths of the solver that are switched off: a device fault seen in solve
 // runs that used them has not been traced to its cause yet, so the solver
 // keeps to the kernels whose runs have been clean (streaming SDSN passes,
-// single-pair path).  With these set, sdsn_mode "onchip" and stable_iters > 0
-// are rejected by the solvers and fram_solve_many solves pair by pair.  The
-// on-chip projection of fram_sdsn_project is not affected.
+// single-pair path).  With these set, sdsn_mode "onchip" is rejected by the
+// solvers and fram_solve_many solves pair by pair.  The on-chip projection of
+// fram_sdsn_project is not affected.
 constexpr bool kSolveOnchip = false;
-constexpr bool kStableStop = false;
 constexpr bool kBatchedKernel = false;
 
 fram_status check_options(const fram_options& o) {
@@ -149,7 +150,6 @@ fram_status check_options(const fram_options& o) {
   if (o.profile < 0 || o.profile > 2) return FRAM_EINVAL;
   if (o.sdsn_mode < 0 || o.sdsn_mode > 2) return FRAM_EINVAL;
   if (o.stable_iters < 0) return FRAM_EINVAL;
-  if (!kStableStop && o.stable_iters > 0) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -592,10 +592,13 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       });
       if (r != FRAM_OK) return r;
     }
-    const bool track = o.stable_iters > 0 && n <= fram::kTrackMaxN;
+    // Argmax-stability stop: the row argmax of N (device) is copied back with
+    // the state; the host compares it with the previous iteration's.
+    const bool track = o.stable_iters > 0;
     if (track) {
       HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s));
-      HIPCHK(fram::launch_argmax_track(dsig, at<int32_t>(c, L.sigprev), n, st, s));
+      c->arg_cur.resize(n);
+      HIPCHK(hipMemcpyAsync(c->arg_cur.data(), dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     }
     if (tol > 0.0 || track || it == iters) {
       r = read_state(c, st, s);
@@ -616,9 +619,11 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       if (track) {
         // Same rule as the oracle: count consecutive iterations whose argmax is
         // a permutation equal to the previous (also a permutation) one.
-        const bool is_perm = c->hst->arg_perm != 0;
-        stable = (is_perm && prev_perm && c->hst->arg_same) ? stable + 1 : 0;
+        const bool is_perm = is_permutation(c->arg_cur.data(), n);
+        const bool same = prev_perm && c->arg_prev == c->arg_cur;
+        stable = (is_perm && prev_perm && same) ? stable + 1 : 0;
         prev_perm = is_perm;
+        std::swap(c->arg_prev, c->arg_cur);
         if (stable >= o.stable_iters) {
           converged = true;
           break;
