@@ -1,3 +1,4 @@
+import os
 import pathlib
 import sys
 
@@ -13,6 +14,8 @@ if str(ROOT) not in sys.path:
 FAULT_SKIP = pytest.mark.skip(
     reason="solver paths that these tests use are switched off: a GPU memory fault or hang "
            "occurred in a run of these tests and its cause is not yet found")
+if os.environ.get("FRAM_RUN_SKIPPED_FAULT_TESTS") == "1":  # explicit re-check of a fix
+    FAULT_SKIP = pytest.mark.gpu
 
 
 def pytest_configure(config):

@@ -14,9 +14,7 @@ import pytest
 import synth
 from oracle import fram64 as O
 
-from conftest import FAULT_SKIP
-
-pytestmark = [pytest.mark.gpu, FAULT_SKIP]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("seed", range(8))

@@ -14,7 +14,6 @@ import pytest
 
 import synth
 from oracle import fram64 as O
-from conftest import FAULT_SKIP
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +76,6 @@ def test_assign_near_permutation_matches_oracle(ctx, n):
     assert paths > 0
 
 
-@FAULT_SKIP
 def test_assign_argmax_permutation_needs_no_path(ctx):
     W = near_permutation(500, seed=3, collide_frac=0.0)
     W[np.arange(500), np.argmax(W, 1)] += 1.0  # argmax rows are a permutation
@@ -87,7 +85,6 @@ def test_assign_argmax_permutation_needs_no_path(ctx):
     assert ctx.last_stats()["lap_paths"] == 0
 
 
-@FAULT_SKIP
 @pytest.mark.parametrize("n,levels", [(60, 3), (257, 2), (1000, 5)])
 def test_assign_with_ties_is_optimal(ctx, n, levels):
     rng = np.random.default_rng(n + levels)
@@ -98,14 +95,12 @@ def test_assign_with_ties_is_optimal(ctx, n, levels):
     assert value(W, p) == value(W, ref)
 
 
-@FAULT_SKIP
 def test_assign_constant_matrix_gives_identity(ctx):
     # Every column ties; rows take columns in order (lowest column on ties).
     p = ctx.assign(np.full((333, 333), 0.25, dtype=np.float32))
     np.testing.assert_array_equal(p, np.arange(333))
 
 
-@FAULT_SKIP
 def test_assign_dev_wide_leading_dimension_and_stream(ctx):
     import torch
     n, ld = 1500, 1536
@@ -120,7 +115,6 @@ def test_assign_dev_wide_leading_dimension_and_stream(ctx):
     np.testing.assert_array_equal(p, O.discretize(W.astype(np.float64)))
 
 
-@FAULT_SKIP
 def test_assign_dev_non_finite_row_is_reported(ctx):
     import torch
     from paper_2508_00887_amd import fram as F
@@ -137,7 +131,6 @@ def test_assign_dev_non_finite_row_is_reported(ctx):
     np.testing.assert_array_equal(ctx.assign(Wh), [3, 2, 1, 0])
 
 
-@FAULT_SKIP
 def test_solve_after_one_iteration_assigns_a_constant_matrix(ctx):
     # After one outer iteration N = alpha 11^T / n exactly (all rows collide):
     # the discretisation is the assignment of a constant matrix.

@@ -223,7 +223,6 @@ def test_onchip_and_streaming_solves_agree(ctx, n, prec):
     assert abs(s1["delta"] - s2["delta"]) <= 1e-12 * max(s1["delta"], 1e-300)
 
 
-@FAULT_SKIP
 @pytest.mark.parametrize("seed", range(6))
 def test_stability_stop_matches_oracle(ctx, seed):
     pr = next(synth.config_pairs(0, [seed]))
