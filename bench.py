@@ -33,10 +33,11 @@ sys.path.insert(0, str(ROOT))
 
 N_WORKLOAD = 4000
 THETA, ITERS, TOL, GAMMA_TOL = 2.0, 100, 1e-6, 1e-6
-# Second stop rule (a stable row argmax of N for this many iterations): off,
-# as the library has the argmax-stability stop switched off; solves stop at
-# delta <= TOL or after ITERS outer iterations.
-STABLE_ITERS = 0
+# Second stop rule: delta has stalled at the floor set by the arithmetic's
+# precision (STALL_ITERS iterations in a row without a new smallest delta,
+# counted once delta <= 1e-3).  BF16/FP16 gradients make delta level off near
+# 1e-4 and FP32 near 1e-6, above the tolerance the FP64 oracle reaches.
+STALL_ITERS = 3
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
@@ -123,7 +124,7 @@ def batched_leg(Context, reps=2):
         t0 = time.perf_counter()
         perms, objs, stats = ctx.solve_many([q.A for q in pairs], [q.B for q in pairs],
                                             theta=THETA, iters=ITERS, tol=TOL, prec="bf16",
-                                            stable_iters=STABLE_ITERS)
+                                            stall_iters=STALL_ITERS)
         dt = time.perf_counter() - t0
         log(f"batched call {r + 1}/{reps}: {dt:.3f}s")
         if best is None or dt < best:
@@ -153,7 +154,7 @@ def served_leg(rate=200.0, duration_s=30.0, warmup_s=5.0, pool=160):
     reqs = [Request(rid=i, A=graphs[i % pool].A, B=graphs[i % pool].B, arrival=t)
             for i, (t, _, _) in enumerate(trace)]
     srv = Server(hbm_budget_bytes=64 << 30, prec="bf16", theta=THETA, iters=ITERS, tol=TOL,
-                 stable_iters=STABLE_ITERS)
+                 stall_iters=STALL_ITERS)
     done = srv.replay(reqs, timeout_s=warmup_s + duration_s + 120.0)
     summ = summarize(done, warmup_s, duration_s)
     acc = [float(np.mean(r.perm == graphs[r.rid % pool].perm)) for r in done if r.perm is not None]
@@ -212,7 +213,7 @@ def main():
     def solve(prec, profile=0):
         return ctx.solve_dev(dA.data_ptr(), dB.data_ptr(), n, theta=THETA, iters=ITERS, tol=TOL,
                              prec=prec, gamma_tol=GAMMA_TOL, stream=stream, profile=profile,
-                             stable_iters=STABLE_ITERS, sdsn_mode=args.sdsn_mode)
+                             stall_iters=STALL_ITERS, sdsn_mode=args.sdsn_mode)
 
     keys = ("ms_gemm", "gemm_launches", "ms_sdsn", "sdsn_launches", "sdsn_passes", "ms_update",
             "ms_stats", "outer_iters")
@@ -282,7 +283,7 @@ def main():
         "config": {"workload": "single pair n=4000, ER p=0.3, U(0,1) weights, noise 0.05, "
                                "10% outliers, seed 2000",
                    "n": n, "theta": THETA, "iters_cap": ITERS, "tol": TOL,
-                   "stable_iters": STABLE_ITERS, "gamma_tol": GAMMA_TOL,
+                   "stall_iters": STALL_ITERS, "gamma_tol": GAMMA_TOL,
                    "gemm_precision": args.prec, "sdsn_mode": args.sdsn_mode},
         "outer_iters": st["outer_iters"], "sdsn_passes": st["sdsn_passes"],
         "accuracy": acc, "objective": obj, "rel_obj_err_vs_oracle": rel_err,
@@ -299,7 +300,7 @@ def main():
                      "passes_per_launch": pm["sdsn_passes"] / max(1, pm["sdsn_launches"])},
         "oracle_accuracy": g["accuracy"] if g else None,
         "oracle_outer_iters": g["outer_iters"] if g else None,
-        "stop_rule": {"tol": TOL, "stable_iters": STABLE_ITERS, "iters_cap": ITERS},
+        "stop_rule": {"tol": TOL, "stall_iters": STALL_ITERS, "iters_cap": ITERS},
     }
     if "fp32" in res:
         line["fp32"] = res["fp32"]

@@ -91,6 +91,8 @@ typedef struct {
   double ms_sdsn;        /* SDSN passes (excluding the final gamma check)              */
   double ms_stats;       /* tile statistics of X that start each SDSN call            */
   double ms_update;      /* N update + delta                                           */
+  int stalled;           /* 1 if the delta-stall rule (fram_options.stall_iters) stopped
+                            the loop                                                   */
 } fram_stats;
 
 typedef struct {
@@ -109,7 +111,15 @@ typedef struct {
                             2 = on-chip: all passes of a projection in one cooperative
                             launch with the iterate held in registers (FRAM_EINVAL if
                             the device cannot hold it)                                */
+  int stall_iters;       /* w > 0: also stop once delta has stalled at the precision's
+                            floor: after delta <= stall_delta, w consecutive iterations
+                            without a new smallest delta; 0 = off (default)            */
+  double stall_delta;    /* delta below which stalls are counted; default 1e-3          */
 } fram_options;
+
+/* Sizes of fram_options and fram_stats as compiled into the library, for
+ * bindings that mirror the structs. */
+void fram_struct_sizes(size_t* options_bytes, size_t* stats_bytes);
 
 typedef struct fram_ctx fram_ctx;
 

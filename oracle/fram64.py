@@ -137,10 +137,27 @@ class FramInfo:
     sdsn_capped: bool
 
 
+def stall_step(count: int, dmin: float | None, delta: float, stall_delta: float):
+    """One iteration of the delta-stall stop (not in the paper): once delta has
+    fallen to stall_delta, count consecutive iterations whose delta is not
+    below the smallest delta seen since then; a new minimum resets the count.
+    Returns the new (count, dmin); the loop stops when count reaches the
+    window.  While delta decreases (at any rate) nothing is counted; at the
+    floor set by the arithmetic's precision delta only fluctuates, and the
+    count soon runs up.  Above stall_delta nothing is counted, so the early
+    phase, where delta need not decrease, never stops the loop."""
+    if delta > stall_delta:
+        return count, dmin
+    count = count + 1 if (dmin is not None and delta >= dmin) else 0
+    dmin = delta if dmin is None else min(dmin, delta)
+    return count, dmin
+
+
 def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
          iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6,
          sdsn_max: int = 1000, N0: np.ndarray | None = None, stable_iters: int = 0,
-         K: np.ndarray | None = None, lam: float = 1.0):
+         K: np.ndarray | None = None, lam: float = 1.0, stall_iters: int = 0,
+         stall_delta: float = 1e-3):
     """Algorithm 1 up to (not including) the discretisation of step 10.
 
     Returns (N, FramInfo).  A and B are the *unscaled* inputs.  K (n x n) is
@@ -152,6 +169,11 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
     has been the same permutation after w consecutive iterations; the loop
     then stops at the first t where argmax(N^(t)) = argmax(N^(t-1)) = ... =
     argmax(N^(t-w)).  A row argmax that is not a permutation never counts.
+
+    stall_iters = w > 0 adds a third stop (not in the paper): delta has reached
+    the floor set by the arithmetic's precision (stall_step); meant for
+    low-precision gradients whose delta levels off above tol.  In FP64 the
+    floor is far below any useful tol.
     """
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
@@ -166,6 +188,7 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
     converged, capped = False, False
     t = 0
     prev_arg, same = None, 0
+    stall, dmin = 0, None
     while True:
         X = As @ N @ Bs                                       # step 5
         if Ks is not None:
@@ -184,6 +207,11 @@ def fram(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
         if delta <= tol:
             converged = True
             break
+        if stall_iters > 0:
+            stall, dmin = stall_step(stall, dmin, delta, stall_delta)
+            if stall >= stall_iters:
+                converged = True
+                break
         if stable_iters > 0:
             arg = np.argmax(N, axis=1)
             is_perm = len(np.unique(arg)) == n
@@ -233,9 +261,10 @@ def accuracy(sigma: np.ndarray, perm: np.ndarray, inlier: np.ndarray | None = No
 
 def solve(A: np.ndarray, B: np.ndarray, theta: float = 2.0, alpha: float = 0.95,
           iters: int = 100, tol: float = 0.0, gamma_th: float = 1e-6, sdsn_max: int = 1000,
-          stable_iters: int = 0, K: np.ndarray | None = None, lam: float = 1.0):
+          stable_iters: int = 0, K: np.ndarray | None = None, lam: float = 1.0,
+          stall_iters: int = 0, stall_delta: float = 1e-3):
     """Full FRAM: Algorithm 1 including step 10; returns (sigma, objective, N, FramInfo)."""
     N, info = fram(A, B, theta, alpha, iters, tol, gamma_th, sdsn_max, stable_iters=stable_iters,
-                   K=K, lam=lam)
+                   K=K, lam=lam, stall_iters=stall_iters, stall_delta=stall_delta)
     sigma = discretize(N)
     return sigma, objective(A, B, sigma, K, lam), N, info

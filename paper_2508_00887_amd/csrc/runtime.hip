@@ -150,6 +150,8 @@ fram_status check_options(const fram_options& o) {
   if (o.profile < 0 || o.profile > 2) return FRAM_EINVAL;
   if (o.sdsn_mode < 0 || o.sdsn_mode > 2) return FRAM_EINVAL;
   if (o.stable_iters < 0) return FRAM_EINVAL;
+  if (o.stall_iters < 0 || !(o.stall_delta > 0.0) || !std::isfinite(o.stall_delta))
+    return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -536,6 +538,9 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   int est = 8;
   int stable = 0;
   bool prev_perm = false;
+  int stall = 0;
+  bool stalled = false;
+  double dmin = 0.0;  // smallest delta since delta first fell to stall_delta (0: not yet)
   Prof prof{o.profile, c, s, 0.0f};
   // The on-chip SDSN inside the outer loop is switched off (see kSolveOnchip);
   // every solve projects with the streaming passes.
@@ -600,7 +605,8 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       c->arg_cur.resize(n);
       HIPCHK(hipMemcpyAsync(c->arg_cur.data(), dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     }
-    if (tol > 0.0 || track || it == iters) {
+    const bool watch_stall = o.stall_iters > 0;
+    if (tol > 0.0 || track || watch_stall || it == iters) {
       r = read_state(c, st, s);
       if (r != FRAM_OK) return r;
       if (c->hst->invalid & 8) {
@@ -615,6 +621,17 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       if (delta <= tol) {
         converged = true;
         break;
+      }
+      if (watch_stall && delta <= o.stall_delta) {
+        // Delta-stall rule (same as the oracle): stall_iters iterations in a
+        // row without a new smallest delta since delta reached stall_delta.
+        stall = (dmin > 0.0 && delta >= dmin) ? stall + 1 : 0;
+        dmin = (dmin > 0.0) ? std::min(dmin, delta) : delta;
+        if (stall >= o.stall_iters) {
+          converged = true;
+          stalled = true;
+          break;
+        }
       }
       if (track) {
         // Same rule as the oracle: count consecutive iterations whose argmax is
@@ -662,6 +679,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   stt->converged = converged ? 1 : 0;
   stt->sdsn_capped = any_capped ? 1 : 0;
   stt->lap_paths = lap_paths;
+  stt->stalled = stalled ? 1 : 0;
   stt->gemm_tile = L.bm;
   stt->delta = delta;
   stt->gamma = gamma;
@@ -759,6 +777,11 @@ fram_status solve_dev_impl(fram_ctx* c, const double* dA, const double* dB, cons
 // ============================================================================ C ABI
 extern "C" {
 
+void fram_struct_sizes(size_t* options_bytes, size_t* stats_bytes) {
+  if (options_bytes) *options_bytes = sizeof(fram_options);
+  if (stats_bytes) *stats_bytes = sizeof(fram_stats);
+}
+
 void fram_default_options(fram_options* opt) {
   if (!opt) return;
   opt->prec = FRAM_FP32;
@@ -769,6 +792,8 @@ void fram_default_options(fram_options* opt) {
   opt->profile = 0;
   opt->sdsn_mode = 0;
   opt->stable_iters = 0;
+  opt->stall_iters = 0;
+  opt->stall_delta = 1e-3;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {

@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
         ("ms_sdsn", ctypes.c_double),
         ("ms_stats", ctypes.c_double),
         ("ms_update", ctypes.c_double),
+        ("stalled", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -59,6 +60,8 @@ class Options(ctypes.Structure):
         ("profile", ctypes.c_int),
         ("stable_iters", ctypes.c_int),
         ("sdsn_mode", ctypes.c_int),
+        ("stall_iters", ctypes.c_int),
+        ("stall_delta", ctypes.c_double),
     ]
 
 
@@ -75,6 +78,7 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 _SIGS = {
     "fram_default_options": (None, [_P]),
+    "fram_struct_sizes": (None, [_P, _P]),
     "fram_create": (_I, [ctypes.POINTER(_P), _I, ctypes.c_size_t]),
     "fram_destroy": (None, [_P]),
     "fram_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I]),
@@ -120,6 +124,11 @@ def load_library():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    ob, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.fram_struct_sizes(ctypes.byref(ob), ctypes.byref(sb))
+    if (ob.value, sb.value) != (ctypes.sizeof(Options), ctypes.sizeof(Stats)):
+        raise ImportError(f"{path}: fram_options / fram_stats are {ob.value} / {sb.value} bytes, "
+                          f"the binding expects {ctypes.sizeof(Options)} / {ctypes.sizeof(Stats)}")
     _lib = lib
     return lib
 
@@ -176,9 +185,12 @@ SDSN_MODES = {"auto": 0, "stream": 1, "onchip": 2}
 
 
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
-             profile=False, sdsn_mode="auto", stable_iters=0) -> Options:
+             profile=False, sdsn_mode="auto", stable_iters=0, stall_iters=0,
+             stall_delta=1e-3) -> Options:
     o = Options()
     o.stable_iters = int(stable_iters)
+    o.stall_iters = int(stall_iters)
+    o.stall_delta = float(stall_delta)
     # profile: False/0 off, True/1 each launch timed alone, 2 timed without
     # serialising the launches.
     o.profile = int(profile)

@@ -79,10 +79,10 @@ class Server:
     def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 3,
                  small_n: int = 512, max_batch: int = 256, prec: str = "bf16",
                  theta: float = 2.0, iters: int = 100, tol: float = 1e-6,
-                 stable_iters: int = 3, device: int = 0, context_factory=None):
+                 stall_iters: int = 3, device: int = 0, context_factory=None):
         self.small_n = small_n
         self.max_batch = max_batch
-        self.opts = dict(prec=prec, stable_iters=stable_iters)
+        self.opts = dict(prec=prec, stall_iters=stall_iters)
         self.theta, self.iters, self.tol = theta, iters, tol
         self.budget = Budget(hbm_budget_bytes)
         self.q_small: deque[Request] = deque()

@@ -80,7 +80,8 @@ def test_invalid_scalars_and_pointers(hctx):
 
 @pytest.mark.parametrize("field,value", [("prec", 7), ("alpha", 0.0), ("alpha", 1.5),
                                          ("gamma_tol", -1.0), ("sdsn_max", 0), ("tile", 96),
-                                         ("profile", 3)])
+                                         ("profile", 3), ("stall_iters", -1),
+                                         ("stall_delta", 0.0), ("stall_delta", float("nan"))])
 def test_invalid_options(hctx, field, value):
     o = F.fram_default_options()
     setattr(o, field, value)
@@ -181,3 +182,11 @@ def test_attributed_solve_rejects_bad_node_input(hctx):
     with pytest.raises(F.FramError) as e:
         hctx.solve(A, A, iters=3, K=np.ones((6, 6)), node_weight=float("inf"))
     assert e.value.status == F.FRAM_EINVAL
+
+
+def test_struct_sizes_match_the_binding():
+    import ctypes
+    lib = F.load_library()
+    ob, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.fram_struct_sizes(ctypes.byref(ob), ctypes.byref(sb))
+    assert ob.value == ctypes.sizeof(F.Options) and sb.value == ctypes.sizeof(F.Stats)

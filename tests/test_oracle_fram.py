@@ -204,3 +204,45 @@ def test_stable_argmax_stop():
     _, info = O.fram(pr.A, pr.B, iters=60, stable_iters=3)
     assert info.outer_iters == t_stop and info.converged
     assert info.deltas == full.deltas[:t_stop]
+
+
+def test_stall_step_counts_only_non_halving_deltas_below_the_threshold():
+    # Early phase above stall_delta: never counted, whatever the trend.
+    c, m = 0, None
+    for d in [1.0, 0.7, 0.8, 0.85, 0.6, 2e-3]:
+        c, m = O.stall_step(c, m, d, 1e-3)
+        assert c == 0 and m is None
+    # Decrease at any rate (0.41 or 0.99 per iteration): every delta is a new
+    # minimum, the count stays 0.
+    for k in range(10):
+        c, m = O.stall_step(c, m, 9e-4 * 0.41 ** k * 0.99 ** k, 1e-3)
+        assert c == 0
+    # A plateau at the precision's floor: counted; a new minimum resets.
+    floor = m
+    counts = []
+    for d in [1.5 * floor, floor, 1.1 * floor, 0.999 * floor, 2.0 * floor]:
+        c, m = O.stall_step(c, m, d, 1e-3)
+        counts.append(c)
+    assert counts == [1, 2, 3, 0, 1]
+
+
+def test_stall_rule_never_fires_while_delta_decreases():
+    # In FP64 delta falls monotonically down to any tol used here (by ~0.85
+    # per iteration on this pair), so the stall rule leaves the run exactly as
+    # delta <= tol alone would.
+    pr = next(synth.config_pairs(0, [0]))
+    _, ref = O.fram(pr.A, pr.B, iters=150, tol=1e-9)
+    _, info = O.fram(pr.A, pr.B, iters=150, tol=1e-9, stall_iters=3)
+    assert ref.converged and info.outer_iters == ref.outer_iters
+    assert info.deltas == ref.deltas
+
+
+def test_stall_rule_stops_at_a_delta_floor():
+    # With tol = 0 the FP64 delta decreases to its rounding floor (~1e-15,
+    # after ~250 iterations on this pair) and only fluctuates there; the rule
+    # stops the run at that floor instead of at the iteration cap.
+    pr = next(synth.config_pairs(0, [0]))
+    _, info = O.fram(pr.A, pr.B, iters=500, tol=0.0, stall_iters=3)
+    assert info.converged and info.outer_iters < 500
+    assert min(info.deltas) < 1e-14
+    assert info.deltas[-1] >= min(info.deltas[:-1])

@@ -122,10 +122,10 @@ def test_served_results_equal_solving_alone():
         for r in done:
             if r.worker == "batched":
                 p, o, _ = ctx.solve_many([r.A], [r.B], iters=100, tol=1e-6, prec="bf16",
-                                         stable_iters=3)
+                                         stall_iters=3)
                 p, o = p[0], o[0]
             else:
-                p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stable_iters=3,
+                p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stall_iters=3,
                                     sdsn_mode="stream")
             np.testing.assert_array_equal(r.perm, p)
             assert r.objective == o
