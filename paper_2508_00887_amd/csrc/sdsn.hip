@@ -67,15 +67,33 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
 
   float s = 1.0f;
   if (PASS) {
-    // One thread reads the flag so that the whole workgroup takes the same
-    // branch even if another workgroup of this launch sets it meanwhile.
+    // Every read of the pass's scalar inputs is issued before the first
+    // barrier: the done flag (one thread, so the whole workgroup takes the
+    // same branch even if another workgroup sets it meanwhile), the tile
+    // totals, and, per thread (p, r), chain p of row r's and of column r's
+    // partial sums (combined in a fixed order below, so the result is that
+    // of summing each chain and combining them in sequence).
     __shared__ int s_done;
-    if (tid == 0) s_done = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (s_done) return;
+    __shared__ double s_chain[2][4][BM];
+    const int done = (tid == 0)
+        ? __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     double part = 0.0;
     for (int t = tid; t < nb * nb; t += NT) part += a.in.tot[t];
-    const double S = block_sum<NT>(part, s_red);
+    float m = -INFINITY;
+    if (a.k == 1)
+      for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
+    {
+      const int r = tid % BM, p = tid / BM;
+      const double* rp = a.in.rowp + bm * BM + r;
+      const double* cp = a.in.colp + bn * BM + r;
+      auto ldr = [&](int b) { return rp[(size_t)b * np]; };
+      auto ldc = [&](int b) { return cp[(size_t)b * np]; };
+      s_chain[0][p][r] = chain_sum(ldr, nb, p);
+      s_chain[1][p][r] = chain_sum(ldc, nb, p);
+    }
+    if (tid == 0) s_done = done;
+    const double S = block_sum<NT>(part, s_red);  // its barriers publish s_done, s_chain
+    if (s_done) return;
     if (a.k >= 2) {
       const double gamma_in = S / n - 1.0;
       if (gamma_in <= a.gamma_tol || a.k > a.max_passes) {
@@ -87,27 +105,19 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
         return;
       }
     } else {
-      float m = -INFINITY;
-      for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
       m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
       s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
     }
     const double sd = (double)s;
     const double dn = (double)n;
     const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
-    for (int r = tid; r < BM; r += NT) {
-      const double* rp = a.in.rowp + bm * BM + r;
-      auto ld = [&](int b) { return rp[(size_t)b * np]; };
-      const double ri = combine4(chain_sum(ld, nb, 0), chain_sum(ld, nb, 1),
-                                 chain_sum(ld, nb, 2), chain_sum(ld, nb, 3));
-      s_a[r] = (float)(half - sd * ri / dn);
-    }
-    for (int c = tid; c < BM; c += NT) {
-      const double* cp = a.in.colp + bn * BM + c;
-      auto ld = [&](int b) { return cp[(size_t)b * np]; };
-      const double cj = combine4(chain_sum(ld, nb, 0), chain_sum(ld, nb, 1),
-                                 chain_sum(ld, nb, 2), chain_sum(ld, nb, 3));
-      s_b[c] = (float)(half - sd * cj / dn);
+    if (tid < BM) {
+      const double ri = combine4(s_chain[0][0][tid], s_chain[0][1][tid], s_chain[0][2][tid],
+                                 s_chain[0][3][tid]);
+      const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
+                                 s_chain[1][3][tid]);
+      s_a[tid] = (float)(half - sd * ri / dn);
+      s_b[tid] = (float)(half - sd * cj / dn);
     }
     __syncthreads();
   } else {
