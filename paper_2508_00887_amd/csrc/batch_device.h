@@ -418,7 +418,7 @@ __device__ void solve_pair(const BatchArgs& A, const BatchPair& P, BatchResult& 
     int paths = 0;
     if (!is_perm) {
       char* base = reinterpret_cast<char*>(&sh);
-      paths = lap_solve<kBT>(Nf, n, (size_t)np, sigma, nullptr,
+      paths = lap_solve<kBT>(Nf, n, (size_t)np, sigma, nullptr, nullptr, 0,
                              lap_carve(base, n, reinterpret_cast<int*>(base + lap_array_bytes(n))),
                              lsh);
     }

@@ -195,9 +195,10 @@ hipError_t launch_copy_f32(const float* src, int ld_src, float* dst, int ld_dst,
 // receives the optimal assignment (all -1 if w admits no finite one); on
 // entry it must hold the row argmax of w (lowest column on ties) when
 // u_ready is set, and u_init[i] = -max_j w[i, j] in FP64 (may point into ws);
-// otherwise the kernel computes both.  ws: lap_workspace_bytes(n) bytes of
-// device memory.  paths_out (may be null) receives the number of rows that
-// needed an augmenting path (0 when the row argmax is a permutation), or -1.
+// otherwise the kernel computes both (and skips the column reduction, which
+// needs u).  ws: lap_workspace_bytes(n) bytes of device memory.  paths_out
+// (may be null) receives the number of rows left unmatched by the row argmax
+// (0 when it is a permutation), or -1.
 struct LapProblem {
   const float* w;
   int n, ld;

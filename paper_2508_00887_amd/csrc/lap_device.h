@@ -7,11 +7,17 @@
 // Hungarian method in its Dijkstra form).  With costs c_ij = -N_ij, dual
 // variables u_i, v_j keep every reduced cost c_ij - u_i - v_j >= 0 and make
 // every matched pair tight.  The start is the dual-feasible partial matching
-// of the row maxima (u_i = min_j c_ij, v = 0): a row keeps its argmax column
-// unless a lower-numbered row took it first.  Each still unmatched row, in
-// increasing order, then grows a shortest-path tree over the columns until it
-// reaches an unmatched column, updates the potentials and flips the path.
-// When the row maxima already form a permutation there is nothing to augment.
+// of the row maxima (u_i = min_j c_ij; v_j = min_i (c_ij - u_i) when the
+// column minima are supplied, else 0): a row keeps its argmax column unless a
+// lower-numbered row took it first.  Two passes of augmenting row reduction
+// (Jonker and Volgenant, 1987) then let the unmatched rows bid: a row takes
+// the column of least reduced cost c_ij - v_j, lowers that column's price
+// until its second choice is as good, and displaces the column's owner, which
+// bids next (bounded in total, so a bidding war cannot run on).  Each row
+// still unmatched, in list order, finally grows a shortest-path tree over the
+// columns until it reaches an unmatched column, updates the potentials and
+// flips the path.  When the row maxima already form a permutation there is
+// nothing to augment.
 //
 // Columns are dealt to threads round-robin and each thread owns the
 // distance, predecessor and scanned flag of its columns, so one step of the
@@ -63,7 +69,29 @@ struct LapShared {
   double wd[2][NW];
   int wj[2][NW];
   int cnt[NW];
+  double b1[NW], b2[NW];  // per-wave best and second-best reduced cost of a bid
+  int c1[NW], c2[NW];     // ... and their columns
 };
+
+// (value, column) pairs in lexicographic order: the lower column wins ties.
+__device__ __forceinline__ bool lap_lex_less(double a, int ja, double b, int jb) {
+  return a < b || (a == b && ja < jb);
+}
+
+// Best two of the union of two sorted pairs (x1 before x2) and (y1 before y2),
+// written as selects so that the values stay in registers.
+__device__ __forceinline__ void lap_top2_merge(double& x1, int& i1, double& x2, int& i2,
+                                               double y1, int k1, double y2, int k2) {
+  const bool yf = lap_lex_less(y1, k1, x1, i1);  // y1 becomes the best
+  // Second best: the better of (x1, y2) if y1 leads, else of (x2, y1).
+  const double ca = yf ? x1 : x2, cb = yf ? y2 : y1;
+  const int ia = yf ? i1 : i2, ib = yf ? k2 : k1;
+  const bool bf = lap_lex_less(cb, ib, ca, ia);
+  x1 = yf ? y1 : x1;
+  i1 = yf ? k1 : i1;
+  x2 = bf ? cb : ca;
+  i2 = bf ? ib : ia;
+}
 
 __device__ __forceinline__ void lap_better(double& d, int& j, double od, int oj) {
   if (od < d || (od == d && oj < j)) {
@@ -76,11 +104,14 @@ __device__ __forceinline__ void lap_better(double& d, int& j, double od, int oj)
 // dimension ld) with the NT threads of the calling workgroup (all must call).
 // sigma: on entry the row argmax (lowest column on ties) when u_init is given,
 // on exit the assignment.  u_init: -max_j W[i, j] in FP64, or null to compute
-// both here.  Returns the number of rows that needed an augmenting path, or
-// -1 (sigma all -1) when W holds values that admit no finite path.
+// both here.  v_part: null, or v_chunks partial column minima of c_ij - u_i
+// (v_part[c * n + j]; only together with u_init).  Returns the number of rows
+// unmatched after the row maxima, or -1 (sigma all -1) when W holds values
+// that admit no finite path.
 template <int NT>
 __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t* sigma,
-                         const double* u_init, LapArrays a, LapShared<NT / 64>& sh) {
+                         const double* u_init, const double* v_part, int v_chunks, LapArrays a,
+                         LapShared<NT / 64>& sh) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -118,7 +149,12 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
     }
   }
   for (int j = tid; j < n; j += NT) {
-    a.v[j] = 0.0;
+    double vj = 0.0;
+    if (v_part != nullptr) {
+      vj = v_part[j];
+      for (int c = 1; c < v_chunks; ++c) vj = fmin(vj, v_part[(size_t)c * n + j]);
+    }
+    a.v[j] = vj;
     a.row_of[j] = INT_MAX;
   }
   __syncthreads();
@@ -152,7 +188,95 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
     __syncthreads();
   }
 
-  // ---- one shortest augmenting path per unmatched row
+  const int unmatched = nfree;
+
+  // ---- augmenting row reduction: unmatched rows bid for columns.  All
+  // threads take the same decisions from the same reduced values; thread 0
+  // writes the matching and the list.  A bid is a fixed amount of work, and
+  // their number is bounded, so this phase always ends.
+  {
+    int budget = 8 * nfree + n;
+    for (int pass = 0; pass < 2 && nfree > 0 && budget > 0; ++pass) {
+      int k = 0, nnext = 0;
+      const int cnt = nfree;
+      while (k < cnt) {
+        if (budget <= 0) {  // carry the rows not yet seen over unchanged
+          if (tid == 0)
+            for (int t = k; t < cnt; ++t) a.freel[nnext + (t - k)] = a.freel[t];
+          nnext += cnt - k;
+          __syncthreads();
+          break;
+        }
+        --budget;
+        const int i = a.freel[k++];
+        const float* ri = W + (size_t)i * ld;
+        double m1 = inf, m2 = inf;
+        int j1 = INT_MAX, j2 = INT_MAX;
+        for (int j = tid; j < n; j += NT) {
+          const double h = -(double)ri[j] - a.v[j];
+          const bool b1 = lap_lex_less(h, j, m1, j1), b2 = lap_lex_less(h, j, m2, j2);
+          m2 = b1 ? m1 : (b2 ? h : m2);
+          j2 = b1 ? j1 : (b2 ? j : j2);
+          m1 = b1 ? h : m1;
+          j1 = b1 ? j : j1;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double y1 = __shfl_xor(m1, o), y2 = __shfl_xor(m2, o);
+          const int k1 = __shfl_xor(j1, o), k2 = __shfl_xor(j2, o);
+          lap_top2_merge(m1, j1, m2, j2, y1, k1, y2, k2);
+        }
+        if (lane == 0) {
+          sh.b1[wave] = m1;
+          sh.b2[wave] = m2;
+          sh.c1[wave] = j1;
+          sh.c2[wave] = j2;
+        }
+        __syncthreads();
+        m1 = sh.b1[0];
+        m2 = sh.b2[0];
+        j1 = sh.c1[0];
+        j2 = sh.c2[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+          lap_top2_merge(m1, j1, m2, j2, sh.b1[w], sh.c1[w], sh.b2[w], sh.c2[w]);
+        if (j2 == INT_MAX) {  // fewer than two finite choices: left to the paths
+          if (tid == 0) a.freel[nnext] = i;
+          ++nnext;
+          __syncthreads();
+          continue;
+        }
+        int i0 = a.row_of[j1];
+        const bool lower = m1 < m2;
+        if (lower) {
+          if (j1 % NT == tid) a.v[j1] -= m2 - m1;
+        } else if (i0 >= 0) {
+          j1 = j2;
+          i0 = a.row_of[j2];
+        }
+        __syncthreads();  // every thread has read row_of before it changes
+        if (tid == 0) {
+          if (i0 >= 0) a.col_of[i0] = -1;
+          a.row_of[j1] = i;
+          a.col_of[i] = j1;
+          a.u[i] = m2;
+        }
+        if (i0 >= 0) {
+          if (lower) {
+            --k;
+            if (tid == 0) a.freel[k] = i0;
+          } else {
+            if (tid == 0) a.freel[nnext] = i0;
+            ++nnext;
+          }
+        }
+        __syncthreads();
+      }
+      nfree = nnext;
+    }
+  }
+
+  // ---- one shortest augmenting path per row still unmatched
   int fail = 0;
   int par = 0;
   for (int k = 0; k < nfree; ++k) {
@@ -236,7 +360,7 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
   }
   for (int i = tid; i < n; i += NT) sigma[i] = fail ? -1 : a.col_of[i];
   __syncthreads();
-  return fail ? -1 : nfree;
+  return fail ? -1 : unmatched;
 }
 
 }  // namespace fram
