@@ -115,6 +115,15 @@ typedef struct {
                             floor: after delta <= stall_delta, w consecutive iterations
                             without a new smallest delta; 0 = off (default)            */
   double stall_delta;    /* delta below which stalls are counted; default 1e-3          */
+  int variant;           /* 0 = FRAM (default); 1 = DSPFP, the baseline iteration FRAM
+                            modifies (Sec. 4, eq. iter.DSPFP): the same outer loop with
+                            the plain alternating doubly stochastic projection of the
+                            unscaled gradient (no theta, no division by max X) for a
+                            fixed dsn_iters passes, stopping on DSPFP's own criterion
+                            max |N/max N - N_prev/max N_prev| <= tol (App. B.2), which
+                            fram_stats.delta then reports.  Solve entry points only;
+                            not with node similarities (FRAM_EINVAL).               */
+  int dsn_iters;         /* DSPFP projection passes per outer iteration; default 30     */
 } fram_options;
 
 /* Sizes of fram_options and fram_stats as compiled into the library, for

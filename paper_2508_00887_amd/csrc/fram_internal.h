@@ -27,6 +27,8 @@ struct DevState {
   double maxB;       // max entry of B (unscaled)
   double maxK;       // max |entry| of the node similarities K (unscaled)
   double objective;  // sum_{k,l} A_kl B_{s(k)s(l)}
+  double nmax;       // max of N after the last update (DSPFP criterion)
+  double nmax_prev;  // ... and before it
 };
 
 // One set of tile partials over an np x np matrix cut into nb x nb tiles of
@@ -69,7 +71,7 @@ hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, i
 // the partials of its input from `in`, writes those of its output to `out`.
 hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
                             DevState* st, int k, int max_passes, double theta,
-                            double gamma_tol, hipStream_t s);
+                            double gamma_tol, hipStream_t s, double fixed_scale = 0.0);
 
 // Arguments of the on-chip SDSN projection (sdsn_persistent.hip).
 struct PersistArgs {
@@ -184,6 +186,14 @@ hipError_t launch_row_argmax(const float* N, int n, int np, int32_t* sigma, hipS
 hipError_t launch_objective(const double* A, const double* B, const int32_t* sigma, int n,
                             double* part, int nblocks, DevState* st, hipStream_t s);
 int objective_blocks(int n);
+
+// DSPFP's outer criterion (App. B.2): st->delta =
+// max_ij |N_ij / max N - P_ij / max P| over the n x n block (ld np), N the
+// iterate after the update and P the one before it; st->nmax_prev takes the
+// previous st->nmax and st->nmax the max of N.  +inf while a maximum is not
+// positive.
+hipError_t launch_dspfp_criterion(const float* N, const float* P, int n, int np, double* part,
+                                  int nblocks, DevState* st, hipStream_t s);
 
 // Copy an n x n float block between leading dimensions.
 hipError_t launch_copy_f32(const float* src, int ld_src, float* dst, int ld_dst, int n,

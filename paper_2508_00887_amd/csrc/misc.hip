@@ -333,6 +333,59 @@ __global__ __launch_bounds__(kT) void copy_f32_kernel(const float* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------ DSPFP criterion
+__global__ __launch_bounds__(kT) void nmax_partial_kernel(const float* __restrict__ N, int n,
+                                                          int np, double* part) {
+  __shared__ double sh[kT];
+  double m = -__builtin_inf();
+  const size_t total = (size_t)n * n;
+  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT)
+    m = fmax(m, (double)N[(t / n) * np + t % n]);
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kT) void nmax_final_kernel(const double* part, int nblocks,
+                                                        DevState* st) {
+  __shared__ double sh[kT];
+  double m = -__builtin_inf();
+  for (int b = threadIdx.x; b < nblocks; b += kT) m = fmax(m, part[b]);
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) {
+    st->nmax_prev = st->nmax;
+    st->nmax = m;
+  }
+}
+
+__global__ __launch_bounds__(kT) void crit_partial_kernel(const float* __restrict__ N,
+                                                          const float* __restrict__ P, int n,
+                                                          int np, const DevState* st,
+                                                          double* part) {
+  __shared__ double sh[kT];
+  const double a = st->nmax, b = st->nmax_prev;
+  double m = 0.0;
+  if (a > 0.0 && b > 0.0) {
+    const size_t total = (size_t)n * n;
+    for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * kT) {
+      const size_t idx = (t / n) * np + t % n;
+      m = fmax(m, fabs((double)N[idx] / a - (double)P[idx] / b));
+    }
+  }
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kT) void crit_final_kernel(const double* part, int nblocks,
+                                                        DevState* st) {
+  __shared__ double sh[kT];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kT) m = fmax(m, part[b]);
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0)
+    st->delta = (st->nmax > 0.0 && st->nmax_prev > 0.0) ? m : __builtin_inf();
+}
+
 int grid_for(size_t work) {
   size_t b = (work + kT - 1) / kT;
   if (b > 2048) b = 2048;
@@ -448,6 +501,15 @@ hipError_t launch_node_term(const double* K, int n, double w, float* dst, int np
 hipError_t launch_node_objective(const double* K, const int32_t* sigma, int n, double w,
                                  DevState* st, hipStream_t s) {
   node_objective_kernel<<<1, kT, 0, s>>>(K, sigma, n, w, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_dspfp_criterion(const float* N, const float* P, int n, int np, double* part,
+                                  int nblocks, DevState* st, hipStream_t s) {
+  nmax_partial_kernel<<<nblocks, kT, 0, s>>>(N, n, np, part);
+  nmax_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  crit_partial_kernel<<<nblocks, kT, 0, s>>>(N, P, n, np, st, part);
+  crit_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct Layout {
   int bm = 64, np = 64, nb = 1;
   Elem e = Elem::F32;
   size_t A64 = 0, B64 = 0, K64 = 0, Kp = 0, Alp = 0, Blp = 0, W = 0, N = 0, Nlp = 0, X = 0;
+  size_t Nprev = 0;  // DSPFP: the iterate before the update
   size_t rowp[2] = {0, 0}, colp[2] = {0, 0}, tot[2] = {0, 0}, tmax[2] = {0, 0};
   size_t upd = 0, mx = 0, obj = 0, sigma = 0, lap = 0, state = 0;
   int nupd = 1, nmax = 1, nobj = 1;
@@ -82,7 +83,7 @@ struct Layout {
 
 enum class Use { Solve, SolveDev, Sdsn, Gradient };
 
-Layout plan(int n, Elem e, int tile, Use use, bool node = false) {
+Layout plan(int n, Elem e, int tile, Use use, bool node = false, bool dspfp = false) {
   Layout L;
   L.e = e;
   L.bm = choose_tile(n, tile);
@@ -111,6 +112,7 @@ Layout plan(int n, Elem e, int tile, Use use, bool node = false) {
   }
   L.X = take(np2 * 4);
   if (use == Use::Solve || use == Use::SolveDev || use == Use::Gradient) L.N = take(np2 * 4);
+  if (dspfp) L.Nprev = take(np2 * 4);
   for (int k = 0; k < 2; ++k) {
     L.rowp[k] = take((size_t)L.nb * L.np * 8);
     L.colp[k] = take((size_t)L.nb * L.np * 8);
@@ -152,6 +154,8 @@ fram_status check_options(const fram_options& o) {
   if (o.stable_iters < 0) return FRAM_EINVAL;
   if (o.stall_iters < 0 || !(o.stall_delta > 0.0) || !std::isfinite(o.stall_delta))
     return FRAM_EINVAL;
+  if (o.variant != 0 && o.variant != 1) return FRAM_EINVAL;
+  if (o.dsn_iters < 1) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -311,7 +315,7 @@ fram_status timed(Prof& p, double* acc, int* cnt, F&& launch) {
 fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevState* st,
                             double theta, const fram_options& o, int first_chunk,
                             hipStream_t s, int* passes, double* gamma, bool* capped,
-                            fram_stats* stt) {
+                            fram_stats* stt, double fixed_scale = 0.0) {
   int k = 1;
   const int last = o.sdsn_max + 1;  // pass index that only evaluates gamma
   int chunk = std::max(2, first_chunk);
@@ -323,7 +327,7 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
       fram_status r = timed(p, nullptr, nullptr, [&] {
         return fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
                                       partials(c, L, kk & 1), st, kk, o.sdsn_max, theta,
-                                      o.gamma_tol, s);
+                                      o.gamma_tol, s, fixed_scale);
       });
       if (r != FRAM_OK) return r;
       r = read_state(c, st, s);
@@ -341,7 +345,7 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
       for (int kk = k; kk <= end; ++kk) {
         const hipError_t e = fram::launch_sdsn_pass(L.bm, X, n, L.np, partials(c, L, (kk - 1) & 1),
                                                     partials(c, L, kk & 1), st, kk, o.sdsn_max,
-                                                    theta, o.gamma_tol, s);
+                                                    theta, o.gamma_tol, s, fixed_scale);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -532,6 +536,29 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   HIPCHK(fram::launch_zero(N, np2 * 4, s));
   if (e != Elem::F32) HIPCHK(fram::launch_zero(Nlp, np2 * fram::elem_size(e), s));
 
+  // DSPFP variant (Sec. 4, eq. iter.DSPFP): the same outer loop, but the
+  // projection is the plain alternating one on the gradient itself (first
+  // pass scale maxA * maxB undoes the prescale; no theta, no division by
+  // max X), with a fixed number of passes, and the outer stop is DSPFP's
+  // max-abs criterion (App. B.2), reported in place of delta.
+  const bool dspfp = o.variant == 1;
+  fram_options os = o;
+  double fixed_scale = 0.0;
+  float* Nprev = nullptr;
+  if (dspfp) {
+    if (nt.K != nullptr) {
+      c->err = "the DSPFP variant takes no node term";
+      return FRAM_EINVAL;
+    }
+    os.gamma_tol = -2.0;  // gamma >= -1 always: never stop early
+    os.sdsn_max = o.dsn_iters;
+    fram_status r = read_state(c, st, s);
+    if (r != FRAM_OK) return r;
+    const double ma = c->hst->maxA, mb = c->hst->maxB;
+    fixed_scale = (ma > 0.0 && mb > 0.0) ? ma * mb : 1.0;
+    Nprev = at<float>(c, L.Nprev);
+  }
+
   int total_passes = 0, last_passes = 0, max_passes_seen = 0, it = 0;
   bool any_capped = false, converged = false;
   double gamma = 0.0, delta = 0.0;
@@ -552,6 +579,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     c->err = "the on-chip SDSN is disabled inside solves (use sdsn_mode stream or auto)";
     return FRAM_EINVAL;
   }
+  if (dspfp) onchip = false;
   for (it = 1; it <= iters; ++it) {
     // Step 5: X = A N B as W = B N^T, X = A W^T.
     fram_status r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
@@ -583,7 +611,8 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       // Step 6: D = SDSN(X, theta), in place in X.
       int passes = 0;
       bool capped = false;
-      r = run_sdsn_passes(c, L, n, X, st, theta, o, est + 1, s, &passes, &gamma, &capped, stt);
+      r = run_sdsn_passes(c, L, n, X, st, theta, os, est + 1, s, &passes, &gamma, &capped, stt,
+                          fixed_scale);
       if (r != FRAM_OK) return r;
       est = passes;
       total_passes += passes;
@@ -591,11 +620,15 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       max_passes_seen = std::max(max_passes_seen, passes);
       any_capped = any_capped || capped;
       // Steps 7-8: N update and delta.
+      if (dspfp) HIPCHK(fram::launch_copy_f32(N, L.np, Nprev, L.np, n, s));
       r = timed(prof, &stt->ms_update, nullptr, [&] {
         return fram::launch_update(e, X, N, Nlp, n, L.np, o.alpha, at<double>(c, L.upd),
                                    L.nupd, st, s);
       });
       if (r != FRAM_OK) return r;
+      if (dspfp)
+        HIPCHK(fram::launch_dspfp_criterion(N, Nprev, n, L.np, at<double>(c, L.mx), L.nmax, st,
+                                            s));
     }
     // Argmax-stability stop: the row argmax of N (device) is copied back with
     // the state; the host compares it with the previous iteration's.
@@ -614,7 +647,8 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
         return FRAM_EDEVICE;
       }
       delta = c->hst->delta;
-      if (!std::isfinite(delta)) {
+      // DSPFP's criterion is +inf while the previous iterate is 0.
+      if (dspfp ? std::isnan(delta) : !std::isfinite(delta)) {
         c->err = "non-finite delta";
         return FRAM_ENUMERIC;
       }
@@ -707,7 +741,7 @@ fram_status solve_host_impl(fram_ctx* c, const double* A, const double* B, const
     stt->ms_total = now_ms() - t0;
     return FRAM_OK;
   }
-  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::Solve, K != nullptr);
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::Solve, K != nullptr, o.variant == 1);
   if (c->budget != 0 && L.total > c->budget) {
     c->err = "workspace exceeds the HBM budget";
     return FRAM_ENOMEM;
@@ -738,7 +772,7 @@ fram_status solve_dev_impl(fram_ctx* c, const double* dA, const double* dB, cons
                            const fram_options& o, int32_t* perm_out, double* objective_out,
                            fram_stats* stats, void* stream) {
   const double t0 = now_ms();
-  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::SolveDev, dK != nullptr);
+  const Layout L = plan(n, (Elem)o.prec, o.tile, Use::SolveDev, dK != nullptr, o.variant == 1);
   if (c->budget != 0 && L.total > c->budget) {
     c->err = "workspace exceeds the HBM budget";
     return FRAM_ENOMEM;
@@ -794,6 +828,8 @@ void fram_default_options(fram_options* opt) {
   opt->stable_iters = 0;
   opt->stall_iters = 0;
   opt->stall_delta = 1e-3;
+  opt->variant = 0;
+  opt->dsn_iters = 30;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -876,6 +912,7 @@ fram_status fram_solve_attr_ex(fram_ctx* c, const double* A, const double* B, co
   if (!c || !A || !B || !K || !perm_out || !objective_out) return FRAM_EINVAL;
   fram_options o = opt ? *opt : defaults();
   fram_status r = check_options(o);
+  if (r == FRAM_OK && o.variant != 0) r = FRAM_EINVAL;  // DSPFP has no node term here
   if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
   if (r == FRAM_OK) r = check_graph(A, n);
   if (r == FRAM_OK) r = check_graph(B, n);
@@ -901,6 +938,7 @@ fram_status fram_solve_attr_dev(fram_ctx* c, const double* dA, const double* dB,
   if (!c || !dA || !dB || !dK || !perm_out || !objective_out) return FRAM_EINVAL;
   fram_options o = opt ? *opt : defaults();
   fram_status r = check_options(o);
+  if (r == FRAM_OK && o.variant != 0) r = FRAM_EINVAL;  // DSPFP has no node term here
   if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
   if (r == FRAM_OK && !std::isfinite(node_weight)) r = FRAM_EINVAL;
   if (r != FRAM_OK) {

@@ -41,6 +41,7 @@ struct TileArgs {
   DevState* st;
   int k, max_passes;
   double theta, gamma_tol;
+  double fixed_scale;  // > 0: first-pass scale s itself, instead of theta / (2 max X)
 };
 
 // PASS = false: statistics of src (and optional padded copy into dst).
@@ -106,7 +107,8 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
       }
     } else {
       m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
-      s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
+      s = (a.fixed_scale > 0.0) ? (float)a.fixed_scale
+                                : ((m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f);
     }
     const double sd = (double)s;
     const double dn = (double)n;
@@ -216,7 +218,7 @@ hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, i
 
 hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
                             DevState* st, int k, int max_passes, double theta,
-                            double gamma_tol, hipStream_t s) {
+                            double gamma_tol, hipStream_t s, double fixed_scale) {
   if (np % bm != 0 || n > np || n < 1 || k < 1) return hipErrorInvalidValue;
   TileArgs a{};
   a.src = X;
@@ -231,6 +233,7 @@ hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partia
   a.max_passes = max_passes;
   a.theta = theta;
   a.gamma_tol = gamma_tol;
+  a.fixed_scale = fixed_scale;
   return launch_tile<true>(bm, a, s);
 }
 

@@ -62,6 +62,8 @@ class Options(ctypes.Structure):
         ("sdsn_mode", ctypes.c_int),
         ("stall_iters", ctypes.c_int),
         ("stall_delta", ctypes.c_double),
+        ("variant", ctypes.c_int),
+        ("dsn_iters", ctypes.c_int),
     ]
 
 
@@ -182,12 +184,15 @@ def _check(ctx: int, st: int, where: str):
 
 
 SDSN_MODES = {"auto": 0, "stream": 1, "onchip": 2}
+VARIANTS = {"fram": 0, "dspfp": 1}
 
 
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
              profile=False, sdsn_mode="auto", stable_iters=0, stall_iters=0,
-             stall_delta=1e-3) -> Options:
+             stall_delta=1e-3, variant="fram", dsn_iters=30) -> Options:
     o = Options()
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.dsn_iters = int(dsn_iters)
     o.stable_iters = int(stable_iters)
     o.stall_iters = int(stall_iters)
     o.stall_delta = float(stall_delta)

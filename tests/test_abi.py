@@ -81,7 +81,8 @@ def test_invalid_scalars_and_pointers(hctx):
 @pytest.mark.parametrize("field,value", [("prec", 7), ("alpha", 0.0), ("alpha", 1.5),
                                          ("gamma_tol", -1.0), ("sdsn_max", 0), ("tile", 96),
                                          ("profile", 3), ("stall_iters", -1),
-                                         ("stall_delta", 0.0), ("stall_delta", float("nan"))])
+                                         ("stall_delta", 0.0), ("stall_delta", float("nan")),
+                                         ("variant", 2), ("variant", -1), ("dsn_iters", 0)])
 def test_invalid_options(hctx, field, value):
     o = F.fram_default_options()
     setattr(o, field, value)
@@ -181,6 +182,13 @@ def test_attributed_solve_rejects_bad_node_input(hctx):
     assert e.value.status == F.FRAM_EINVAL
     with pytest.raises(F.FramError) as e:
         hctx.solve(A, A, iters=3, K=np.ones((6, 6)), node_weight=float("inf"))
+    assert e.value.status == F.FRAM_EINVAL
+
+
+def test_dspfp_variant_rejects_node_similarities(hctx):
+    A = _graph()
+    with pytest.raises(F.FramError) as e:
+        hctx.solve(A, A, iters=3, K=np.ones((6, 6)), variant="dspfp")
     assert e.value.status == F.FRAM_EINVAL
 
 

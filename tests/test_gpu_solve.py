@@ -295,3 +295,34 @@ def test_n4000_stall_stop_accuracy_gate(ctx, prec):
     assert abs(obj - host_objective(pr.A, pr.B, perm)) <= 1e-12 * abs(obj)
     assert abs(obj - g["objective"]) <= 1e-3 * abs(g["objective"])
     assert O.accuracy(perm, pr.perm, pr.inlier) >= g["accuracy"] - 0.005
+
+
+# ---------------------------------------------------------------- DSPFP variant
+from oracle import dspfp64 as P  # noqa: E402
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dspfp_variant_equals_oracle(ctx, seed):
+    # The baseline iteration (Sec. 4): FP32 GEMMs give the FP64 oracle's
+    # permutation; the max-abs criterion trajectory is the oracle's, so the
+    # stop iteration matches within one.
+    pr = next(synth.config_pairs(0, [seed]))
+    s_or, obj_or, _, info = P.solve(pr.A, pr.B, iters=60, tol=1e-4)
+    perm, obj, st = ctx.solve(pr.A, pr.B, iters=60, tol=1e-4, prec="fp32", variant="dspfp")
+    np.testing.assert_array_equal(perm, s_or)
+    assert abs(obj - obj_or) <= 1e-5 * abs(obj_or)
+    assert abs(st["outer_iters"] - info.outer_iters) <= 1
+    assert st["sdsn_passes"] == 30 * st["outer_iters"]
+
+
+def test_dspfp_is_scale_sensitive_fram_is_not(ctx):
+    # Sec. 5.1 on the device: scaling both graphs changes DSPFP's projected
+    # iterates (here its criterion trajectory), never FRAM's.
+    pr = synth.make_pair(120, 0.4, 0.05, 5151)
+    s1 = ctx.solve(pr.A, pr.B, iters=8, prec="fp32", variant="dspfp")[2]
+    s2 = ctx.solve(10 * pr.A, 10 * pr.B, iters=8, prec="fp32", variant="dspfp")[2]
+    assert abs(s1["delta"] - s2["delta"]) > 1e-3 * max(s1["delta"], s2["delta"])
+    f1 = ctx.solve(pr.A, pr.B, iters=8, prec="fp32")
+    f2 = ctx.solve(10 * pr.A, 10 * pr.B, iters=8, prec="fp32")
+    np.testing.assert_array_equal(f1[0], f2[0])
+    assert f1[2]["sdsn_passes"] == f2[2]["sdsn_passes"]
