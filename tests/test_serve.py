@@ -7,7 +7,6 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import FAULT_SKIP
 from paper_2508_00887_amd.serve import Budget, Request, Server, summarize
 
 
@@ -104,7 +103,6 @@ def test_admission_respects_budget():
 
 
 @pytest.mark.gpu
-@FAULT_SKIP
 def test_served_results_equal_solving_alone():
     from paper_2508_00887_amd import Context
     rng = np.random.default_rng(4000)
