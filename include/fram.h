@@ -66,6 +66,11 @@ typedef enum {
  * with TF32 replaced by FP16 or BF16, which gfx950 MFMA provides). */
 typedef enum { FRAM_FP32 = 0, FRAM_BF16 = 1, FRAM_FP16 = 2 } fram_precision;
 
+/* Largest n any entry point takes (FRAM_EINVAL above it): the padded n x n
+ * FP32 iterate must stay below 4 GiB, the range of the kernels' 32-bit
+ * element offsets.  The workspace at this size is about 40 GB. */
+#define FRAM_MAX_N 32768
+
 typedef struct {
   int outer_iters;       /* outer iterations run (Algorithm 1 loop)                    */
   int sdsn_passes;       /* SDSN passes summed over all outer iterations               */

@@ -160,7 +160,7 @@ fram_status check_options(const fram_options& o) {
 }
 
 fram_status check_scalars(int n, double theta, int iters, double tol) {
-  if (n < 1) return FRAM_EINVAL;
+  if (n < 1 || n > FRAM_MAX_N) return FRAM_EINVAL;
   if (!(theta > 0.0) || !std::isfinite(theta)) return FRAM_EINVAL;
   if (iters < 1) return FRAM_EINVAL;
   if (!(tol >= 0.0) || !std::isfinite(tol)) return FRAM_EINVAL;
@@ -858,7 +858,7 @@ void fram_destroy(fram_ctx* c) {
 }
 
 size_t fram_workspace_bytes(int n, fram_precision prec, int tile) {
-  if (n < 1 || !valid_prec((int)prec)) return 0;
+  if (n < 1 || n > FRAM_MAX_N || !valid_prec((int)prec)) return 0;
   return plan(n, (Elem)prec, tile, Use::Solve).total;
 }
 
@@ -955,7 +955,8 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   if (!c || !dK || !dX) return FRAM_EINVAL;
   fram_options o = opt ? *opt : defaults();
   fram_status r = check_options(o);
-  if (r != FRAM_OK || n < 1 || ldk < n || ldx < n || !(lambda > 0.0) || !std::isfinite(lambda)) {
+  if (r != FRAM_OK || n < 1 || n > FRAM_MAX_N || ldk < n || ldx < n || ldk > FRAM_MAX_N ||
+      ldx > FRAM_MAX_N || !(lambda > 0.0) || !std::isfinite(lambda)) {
     c->err = "invalid argument";
     return FRAM_EINVAL;
   }
@@ -1028,7 +1029,7 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
 
 fram_status fram_sdsn_project_ex(fram_ctx* c, const float* K, int n, double lambda,
                                  const fram_options* opt, float* X_out, fram_stats* stats) {
-  if (!c || !K || !X_out || n < 1) return FRAM_EINVAL;
+  if (!c || !K || !X_out || n < 1 || n > FRAM_MAX_N) return FRAM_EINVAL;
   fram_options o = opt ? *opt : defaults();
   if (check_options(o) != FRAM_OK || !(lambda > 0.0) || !std::isfinite(lambda)) return FRAM_EINVAL;
   for (size_t t = 0; t < (size_t)n * n; ++t)
@@ -1059,7 +1060,8 @@ fram_status fram_sdsn_project(fram_ctx* c, const float* K, int n, double lambda,
 
 fram_status fram_gradient(fram_ctx* c, const float* A, const float* N, const float* B, int n,
                           fram_precision prec, float* X_out) {
-  if (!c || !A || !N || !B || !X_out || n < 1 || !valid_prec((int)prec)) return FRAM_EINVAL;
+  if (!c || !A || !N || !B || !X_out || n < 1 || n > FRAM_MAX_N || !valid_prec((int)prec))
+    return FRAM_EINVAL;
   const Elem e = (Elem)prec;
   const Layout L = plan(n, e, 0, Use::Gradient);
   if (c->budget != 0 && L.total > c->budget) {
@@ -1333,7 +1335,7 @@ fram_status assign_on_device(fram_ctx* c, const float* dW, int ldw, int n, int32
 }  // namespace
 
 fram_status fram_assign(fram_ctx* c, const float* W, int n, int32_t* perm_out) {
-  if (!c || !W || !perm_out || n < 1) return FRAM_EINVAL;
+  if (!c || !W || !perm_out || n < 1 || n > FRAM_MAX_N) return FRAM_EINVAL;
   for (size_t t = 0; t < (size_t)n * n; ++t)
     if (!std::isfinite(W[t])) return FRAM_EINVAL;
   const size_t wbytes = align_up((size_t)n * n * 4);
@@ -1355,7 +1357,8 @@ fram_status fram_assign(fram_ctx* c, const float* W, int n, int32_t* perm_out) {
 
 fram_status fram_assign_dev(fram_ctx* c, const float* dW, int ldw, int n, int32_t* dperm,
                             void* stream) {
-  if (!c || !dW || !dperm || n < 1 || ldw < n) return FRAM_EINVAL;
+  if (!c || !dW || !dperm || n < 1 || n > FRAM_MAX_N || ldw < n || ldw > FRAM_MAX_N)
+    return FRAM_EINVAL;
   fram_status r = ensure_device(c);
   if (r != FRAM_OK) return r;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;

@@ -198,3 +198,18 @@ def test_struct_sizes_match_the_binding():
     ob, sb = ctypes.c_size_t(), ctypes.c_size_t()
     lib.fram_struct_sizes(ctypes.byref(ob), ctypes.byref(sb))
     assert ob.value == ctypes.sizeof(F.Options) and sb.value == ctypes.sizeof(F.Stats)
+
+
+def test_sizes_above_the_maximum_are_rejected_before_device_use(hctx):
+    # FRAM_MAX_N = 32768 (32-bit element offsets of the padded FP32 iterate).
+    import ctypes
+    n = 32769
+    A = np.zeros(1)  # never read: the size check comes first
+    perm = np.zeros(1, dtype=np.int32)
+    obj = ctypes.c_double()
+    st = hctx.lib.fram_solve(hctx.handle, A.ctypes.data, A.ctypes.data, n, 2.0, 5, 0.0,
+                             perm.ctypes.data, ctypes.byref(obj))
+    assert st == F.FRAM_EINVAL
+    assert hctx.lib.fram_workspace_bytes(n, 0, 0) == 0
+    W = np.zeros(1, dtype=np.float32)
+    assert hctx.lib.fram_assign(hctx.handle, W.ctypes.data, n, perm.ctypes.data) == F.FRAM_EINVAL

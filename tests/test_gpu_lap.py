@@ -65,8 +65,8 @@ def test_assign_random_matches_oracle(ctx, n):
     assert value(W, p) == value(W, ref)
 
 
-# 4000 keeps the assignment's arrays in LDS; 4500 and 6000 use the workspace.
-@pytest.mark.parametrize("n", [64, 777, 2048, 4000, 4500, 6000])
+# 4000 keeps the assignment's arrays in LDS; 4500, 6000 and 10000 use the workspace.
+@pytest.mark.parametrize("n", [64, 777, 2048, 4000, 4500, 6000, 10000])
 def test_assign_near_permutation_matches_oracle(ctx, n):
     W = near_permutation(n, seed=n, collide_frac=0.05)
     p = ctx.assign(W)

@@ -116,6 +116,21 @@ def test_n4000_full_size_properties(ctx):
     assert st["gemm_tile"] == 256
 
 
+@pytest.mark.parametrize("n", [4097, 6000])
+def test_large_ragged_solve_properties(ctx, n):
+    # Past the n = 4000 workload: a ragged tile grid (4097 = 16 tiles of 256
+    # plus one row) and the assignment's global-memory mode (n > 4400).  No
+    # stored oracle run: a valid permutation, the FP64 objective of exactly
+    # that permutation, and the planted inliers recovered.
+    pr = synth.make_pair(n, 0.3, 0.05, 9100 + n, outlier_frac=0.1)
+    perm, obj, st = ctx.solve(pr.A, pr.B, theta=2.0, iters=100, tol=1e-6, prec="bf16",
+                              stall_iters=3)
+    check_perm(perm, n)
+    assert abs(obj - host_objective(pr.A, pr.B, perm)) <= 1e-12 * abs(obj)
+    assert O.accuracy(perm, pr.perm, pr.inlier) > 0.9
+    assert st["converged"] == 1 and st["outer_iters"] < 100
+
+
 def test_tolerance_stops_like_the_oracle(ctx):
     pr = synth.make_pair(120, 0.5, 0.05, 4242)
     _, full = O.fram(pr.A, pr.B, iters=80)
