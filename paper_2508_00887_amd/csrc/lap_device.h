@@ -93,11 +93,70 @@ __device__ __forceinline__ void lap_top2_merge(double& x1, int& i1, double& x2, 
   i2 = bf ? ib : ia;
 }
 
+// Lane exchanges inside a 16-lane DPP row (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ int lap_dpp(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double lap_dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = lap_dpp<CTRL>((int)b), hi = lap_dpp<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double lap_readlane(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ void lap_better(double& d, int& j, double od, int oj) {
   if (od < d || (od == d && oj < j)) {
     d = od;
     j = oj;
   }
+}
+
+// Lexicographic minimum of (d, j) over the 64 lanes of a wave, in every
+// lane: a butterfly inside each DPP row (neighbour, pair, half-row mirror,
+// row mirror), then the four row results.  The minimum of a total order does
+// not depend on the order of combination.  All 64 lanes must take part.
+__device__ __forceinline__ void lap_wave_min(double& d, int& j) {
+  lap_better(d, j, lap_dpp<0xB1>(d), lap_dpp<0xB1>(j));
+  lap_better(d, j, lap_dpp<0x4E>(d), lap_dpp<0x4E>(j));
+  lap_better(d, j, lap_dpp<0x141>(d), lap_dpp<0x141>(j));
+  lap_better(d, j, lap_dpp<0x140>(d), lap_dpp<0x140>(j));
+  double r = lap_readlane(d, 0);
+  int rj = __builtin_amdgcn_readlane(j, 0);
+#pragma unroll
+  for (int row = 16; row < 64; row += 16)
+    lap_better(r, rj, lap_readlane(d, row), __builtin_amdgcn_readlane(j, row));
+  d = r;
+  j = rj;
+}
+
+// Best two (value, column) pairs over the 64 lanes of a wave, in every lane,
+// the same way.
+__device__ __forceinline__ void lap_wave_top2(double& m1, int& j1, double& m2, int& j2) {
+#define LAP_TOP2_STEP(CTRL)                                                            \
+  lap_top2_merge(m1, j1, m2, j2, lap_dpp<CTRL>(m1), lap_dpp<CTRL>(j1), lap_dpp<CTRL>(m2), \
+                 lap_dpp<CTRL>(j2))
+  LAP_TOP2_STEP(0xB1);
+  LAP_TOP2_STEP(0x4E);
+  LAP_TOP2_STEP(0x141);
+  LAP_TOP2_STEP(0x140);
+#undef LAP_TOP2_STEP
+  double r1 = lap_readlane(m1, 0), r2 = lap_readlane(m2, 0);
+  int k1 = __builtin_amdgcn_readlane(j1, 0), k2 = __builtin_amdgcn_readlane(j2, 0);
+#pragma unroll
+  for (int row = 16; row < 64; row += 16)
+    lap_top2_merge(r1, k1, r2, k2, lap_readlane(m1, row), __builtin_amdgcn_readlane(j1, row),
+                   lap_readlane(m2, row), __builtin_amdgcn_readlane(j2, row));
+  m1 = r1;
+  j1 = k1;
+  m2 = r2;
+  j2 = k2;
 }
 
 // Solves max_sigma sum_i W[i, sigma(i)] for the n x n block of W (leading
@@ -220,12 +279,7 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
           m1 = b1 ? h : m1;
           j1 = b1 ? j : j1;
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const double y1 = __shfl_xor(m1, o), y2 = __shfl_xor(m2, o);
-          const int k1 = __shfl_xor(j1, o), k2 = __shfl_xor(j2, o);
-          lap_top2_merge(m1, j1, m2, j2, y1, k1, y2, k2);
-        }
+        lap_wave_top2(m1, j1, m2, j2);
         if (lane == 0) {
           sh.b1[wave] = m1;
           sh.b2[wave] = m2;
@@ -300,8 +354,7 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
           bd = a.dist[j];
           bj = j;
         }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) lap_better(bd, bj, __shfl_xor(bd, o), __shfl_xor(bj, o));
+      lap_wave_min(bd, bj);
       if (lane == 0) {
         sh.wd[par][wave] = bd;
         sh.wj[par][wave] = bj;
