@@ -31,6 +31,7 @@ import time
 ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
+
 N_WORKLOAD = 4000
 THETA, ITERS, TOL, GAMMA_TOL = 2.0, 100, 1e-6, 1e-6
 # Second stop rule: delta has stalled at the floor set by the arithmetic's

@@ -13,7 +13,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -52,6 +55,9 @@ struct fram_ctx {
   // Argmax-stability stop: the row argmax of N of this and of the previous
   // outer iteration (host copies).
   std::vector<int32_t> arg_cur, arg_prev;
+  // fram_solve_many: worker contexts (own stream and workspace each), made on
+  // first use and kept until fram_destroy.
+  std::vector<fram_ctx*> workers;
 };
 
 namespace {
@@ -142,6 +148,8 @@ bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP
 // fram_sdsn_project is not affected.
 constexpr bool kSolveOnchip = false;
 constexpr bool kBatchedKernel = false;
+// Most worker contexts of one fram_solve_many call (fram_options.many_workers).
+constexpr int kMaxManyWorkers = 32;
 
 fram_status check_options(const fram_options& o) {
   if (!valid_prec((int)o.prec)) return FRAM_EINVAL;
@@ -156,6 +164,7 @@ fram_status check_options(const fram_options& o) {
     return FRAM_EINVAL;
   if (o.variant != 0 && o.variant != 1) return FRAM_EINVAL;
   if (o.dsn_iters < 1) return FRAM_EINVAL;
+  if (o.many_workers < 1 || o.many_workers > kMaxManyWorkers) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -830,6 +839,7 @@ void fram_default_options(fram_options* opt) {
   opt->stall_delta = 1e-3;
   opt->variant = 0;
   opt->dsn_iters = 30;
+  opt->many_workers = 8;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -844,7 +854,9 @@ fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
 
 void fram_destroy(fram_ctx* c) {
   if (!c) return;
+  for (fram_ctx* w : c->workers) fram_destroy(w);
   if (c->inited) {
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ws) (void)hipFree(c->ws);
@@ -1275,13 +1287,53 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
     if (r != FRAM_OK) return r;
   }
   // Pairs too large for one workgroup (all pairs while the batched kernel is
-  // switched off) go through the single-pair path.
-  for (int p : single) {
-    fram_stats st{};
-    r = solve_host_impl(c, A[p], B[p], nullptr, 0.0, n[p], lambda, iters, tol, o, perm_out[p],
-                        &objective_out[p], &st);
-    if (stats) stats[p] = st;
-    if (r != FRAM_OK) return r;
+  // switched off) go through the single-pair path: up to o.many_workers pairs
+  // at a time, each on a worker context with its own stream and workspace
+  // (one host thread per worker), largest pairs first.  Each pair's result
+  // is that of solving it alone: nothing is shared between the workers but
+  // the device.
+  if (!single.empty()) {
+    std::stable_sort(single.begin(), single.end(), [&](int x, int y) { return n[x] > n[y]; });
+    const int nw = (int)std::min<size_t>((size_t)o.many_workers, single.size());
+    while ((int)c->workers.size() < nw) {
+      fram_ctx* w = nullptr;
+      // The context's HBM budget is shared out evenly between its workers.
+      r = fram_create(&w, c->device, c->budget == 0 ? 0 : c->budget / kMaxManyWorkers);
+      if (r != FRAM_OK) return r;
+      c->workers.push_back(w);
+    }
+    std::atomic<int> next{0};
+    std::atomic<int> failed{0};
+    std::mutex mu;
+    fram_status first = FRAM_OK;
+    auto work = [&](fram_ctx* w) {
+      while (!failed.load()) {
+        const int q = next.fetch_add(1);
+        if (q >= (int)single.size()) return;
+        const int p = single[q];
+        fram_stats st{};
+        const fram_status rr = solve_host_impl(w, A[p], B[p], nullptr, 0.0, n[p], lambda, iters,
+                                               tol, o, perm_out[p], &objective_out[p], &st);
+        if (stats) stats[p] = st;
+        if (rr != FRAM_OK) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (first == FRAM_OK) {
+            first = rr;
+            c->err = "pair " + std::to_string(p) + ": " + w->err;
+          }
+          failed.store(1);
+          return;
+        }
+      }
+    };
+    if (nw == 1) {
+      work(c->workers[0]);
+    } else {
+      std::vector<std::thread> th;
+      for (int t = 0; t < nw; ++t) th.emplace_back(work, c->workers[t]);
+      for (auto& t : th) t.join();
+    }
+    if (first != FRAM_OK) return first;
   }
   const double ms = now_ms() - t0;
   if (stats)

@@ -64,6 +64,7 @@ class Options(ctypes.Structure):
         ("stall_delta", ctypes.c_double),
         ("variant", ctypes.c_int),
         ("dsn_iters", ctypes.c_int),
+        ("many_workers", ctypes.c_int),
     ]
 
 
@@ -189,8 +190,9 @@ VARIANTS = {"fram": 0, "dspfp": 1}
 
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
              profile=False, sdsn_mode="auto", stable_iters=0, stall_iters=0,
-             stall_delta=1e-3, variant="fram", dsn_iters=30) -> Options:
+             stall_delta=1e-3, variant="fram", dsn_iters=30, many_workers=8) -> Options:
     o = Options()
+    o.many_workers = int(many_workers)
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.dsn_iters = int(dsn_iters)
     o.stable_iters = int(stable_iters)

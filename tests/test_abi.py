@@ -82,7 +82,8 @@ def test_invalid_scalars_and_pointers(hctx):
                                          ("gamma_tol", -1.0), ("sdsn_max", 0), ("tile", 96),
                                          ("profile", 3), ("stall_iters", -1),
                                          ("stall_delta", 0.0), ("stall_delta", float("nan")),
-                                         ("variant", 2), ("variant", -1), ("dsn_iters", 0)])
+                                         ("variant", 2), ("variant", -1), ("dsn_iters", 0),
+                                         ("many_workers", 0), ("many_workers", 33)])
 def test_invalid_options(hctx, field, value):
     o = F.fram_default_options()
     setattr(o, field, value)
