@@ -13,9 +13,10 @@
 // (64 bf16/f16 or 32 f32 elements) through a two-stage LDS ring with a
 // register prefetch of the next stage.  LDS rows are 128 bytes; the 16-byte
 // chunk index is XOR-swizzled with the row so the 128-bit reads of 32
-// consecutive rows spread over the banks.  Tiles are assigned so that
-// consecutive tiles (same row strip of P) land on the same XCD and share its
-// L2.
+// consecutive rows spread over the banks.  Tiles are assigned so that the
+// tiles of one XCD form a compact block of the tile grid (half its rows by a
+// quarter of its columns), which keeps the row and column panels that XCD's
+// L2 must hold few.
 #include "fram_internal.h"
 
 namespace fram {
@@ -89,11 +90,19 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int nbn = np / BM;
-  int bid = blockIdx.x;
+  const int bid = blockIdx.x;
   const int ntiles = gridDim.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int m0 = (bid / nbn) * BM;
-  const int n0 = (bid % nbn) * BM;
+  int tm = bid / nbn, tn = bid % nbn;
+  if ((ntiles & 7) == 0 && (nbn & 1) == 0 && ((nbn / 2) & 3) == 0) {
+    // Workgroup bid runs on XCD bid % 8.  XCD x takes the x-th block of the
+    // tile grid cut into 2 x 4 blocks (nbn/2 tile rows by nbn/4 tile columns).
+    const int x = bid & 7, k = bid >> 3;
+    const int bh = nbn / 2, bw = nbn / 4;
+    tm = (x >> 2) * bh + k / bw;
+    tn = (x & 3) * bw + k % bw;
+  }
+  const int m0 = tm * BM;
+  const int n0 = tn * BM;
   const int wm = wave >> 1, wn = wave & 1;
   const int ldc = ld / Mfma<E>::kPerChunk;  // leading dimension in chunks
 
