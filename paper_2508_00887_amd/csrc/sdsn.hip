@@ -79,19 +79,34 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     const int done = (tid == 0)
         ? __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     double part = 0.0;
-    for (int t = tid; t < nb * nb; t += NT) part += a.in.tot[t];
     float m = -INFINITY;
-    if (a.k == 1)
-      for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
-    {
-      const int r = tid % BM, p = tid / BM;
-      const double* rp = a.in.rowp + bm * BM + r;
-      const double* cp = a.in.colp + bn * BM + r;
-      auto ldr = [&](int b) { return rp[(size_t)b * np]; };
-      auto ldc = [&](int b) { return cp[(size_t)b * np]; };
-      s_chain[0][p][r] = chain_sum(ldr, nb, p);
-      s_chain[1][p][r] = chain_sum(ldc, nb, p);
+    double rsum, csum;
+    const int r = tid % BM, p = tid / BM;
+    const double* rp = a.in.rowp + bm * BM + r;
+    const double* cp = a.in.colp + bn * BM + r;
+    auto ldr = [&](int b) { return rp[(size_t)b * np]; };
+    auto ldc = [&](int b) { return cp[(size_t)b * np]; };
+    if (nb <= 16) {
+      // Then nb * nb <= NT: one total (and first-pass maximum) per thread,
+      // read with the chains before any of them is used, so the whole
+      // prologue waits for memory once.  The maxima buffer is valid on every
+      // pass; its values are used on the first.
+      const bool has_t = tid < nb * nb;
+      const int t = has_t ? tid : 0;
+      const double tv = a.in.tot[t];
+      const float mv = a.in.tmax[t];
+      chain_sum_pair16(ldr, ldc, nb, p, rsum, csum);
+      part = has_t ? part + tv : part;
+      m = (has_t && a.k == 1) ? fmaxf(m, mv) : m;
+    } else {
+      for (int t = tid; t < nb * nb; t += NT) part += a.in.tot[t];
+      if (a.k == 1)
+        for (int t = tid; t < nb * nb; t += NT) m = fmaxf(m, a.in.tmax[t]);
+      rsum = chain_sum(ldr, nb, p);
+      csum = chain_sum(ldc, nb, p);
     }
+    s_chain[0][p][r] = rsum;
+    s_chain[1][p][r] = csum;
     if (tid == 0) s_done = done;
     const double S = block_sum<NT>(part, s_red);  // its barriers publish s_done, s_chain
     if (s_done) return;

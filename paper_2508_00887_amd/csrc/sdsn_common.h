@@ -57,6 +57,32 @@ __device__ __forceinline__ double chain_sum(LoadF load, int nb, int p) {
   return acc;
 }
 
+// Chain p of a row's and of a column's partial sums at once, for nb <= 16
+// tiles, with the arithmetic of chain_sum.  All eight loads are issued before
+// the first add (an index past the end is clamped to tile nb - 1 and its value
+// dropped), so both chains together cost one memory round trip.
+template <typename LoadR, typename LoadC>
+__device__ __forceinline__ void chain_sum_pair16(LoadR ldr, LoadC ldc, int nb, int p, double& rs,
+                                                 double& cs) {
+  double rv[4], cv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = p + 4 * q;
+    const int bc = b < nb ? b : nb - 1;
+    rv[q] = ldr(bc);
+    cv[q] = ldc(bc);
+  }
+  double ra = 0.0, ca = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool in = p + 4 * q < nb;
+    ra = in ? ra + rv[q] : ra;
+    ca = in ? ca + cv[q] : ca;
+  }
+  rs = ra;
+  cs = ca;
+}
+
 __device__ __forceinline__ double combine4(double c0, double c1, double c2, double c3) {
   return (c0 + c1) + (c2 + c3);
 }
