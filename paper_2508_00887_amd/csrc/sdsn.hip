@@ -159,7 +159,10 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     const int rl = w * 16 + stp * RPW + q;
     const int i = bm * BM + rl;
     float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < n) {
+    // In a pass, lanes whose four columns all lie past n (the padding of the
+    // last column tile, zero since the matrix was written) neither read nor
+    // write: the pass would only store zeros there again.
+    if (i < n && (!PASS || c0)) {
       if (PASS) {
         float4* row = reinterpret_cast<float4*>(a.dst + (size_t)i * np + j);
         const float4 x = *row;
