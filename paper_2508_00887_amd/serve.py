@@ -6,10 +6,11 @@ few worker contexts, each with its own HIP stream and workspace, so the
 kernels of different requests overlap on the device:
 
 * requests with n <= ``small_n`` are gathered by the batching worker, which
-  takes every small request waiting when it becomes free and solves them in
-  one launch of the batched kernel (fram_solve_many) -- one workgroup per
-  request, so a request's result is the same whether it ran alone or with
-  others;
+  takes every small request waiting when it becomes free and hands them to
+  fram_solve_many in one call; that call solves the pairs concurrently on its
+  own worker contexts (a stream each), and every pair runs exactly the
+  single-pair solve, so a request's result is the same whether it ran alone
+  or with others;
 * larger requests go to the single-pair workers (fram_solve_ex) with
   per-pass SDSN launches, which share the device with whatever else runs.
 
