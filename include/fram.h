@@ -158,6 +158,26 @@ void fram_destroy(fram_ctx* ctx);
  * the budget check and by admission control.  Pure host arithmetic. */
 size_t fram_workspace_bytes(int n, fram_precision prec, int tile);
 
+/* Autotune table for the automatic tile choice (fram_options.tile == 0): the
+ * square tile edge of the SDSN passes and GEMMs of a solve or projection of
+ * size n.  Bucket k covers n_max[k-1] < n <= n_max[k] (n_max strictly
+ * increasing, >= 1) and selects tile[k] (64, 128 or 256); sizes above the
+ * last bucket keep the built-in rule (the largest tile whose grid has at
+ * least 200 tiles, else 64).  The table is copied; it is shared by every
+ * context of the process and also governs fram_workspace_bytes(.., 0).
+ * count == 0 clears it.  At most 64 buckets.  Returns FRAM_EINVAL (table
+ * unchanged) on a count out of range, a NULL array with count > 0, an
+ * n_max that is not strictly increasing and positive, or a tile not in
+ * {64, 128, 256}.  Calls that race with solves being planned on other
+ * threads are safe; each solve uses the table as it was when it started.
+ * Results can differ in the last bits between tile edges (the FP64 partial
+ * sums of the SDSN pass are combined per tile). */
+fram_status fram_set_tile_table(const int* n_max, const int* tile, int count);
+
+/* Tile edge the automatic choice gives for size n (table, else built-in
+ * rule); 0 when n is outside [1, FRAM_MAX_N].  Pure host arithmetic. */
+int fram_auto_tile(int n);
+
 /* FRAM, Algorithm 1 (with Algorithm 2 as its projection), on host inputs.
  *   A, B      host, n*n doubles, row-major; symmetric, finite, >= 0 (Sec. 3).
  *   n         >= 1.  n == 1 returns perm {0}.

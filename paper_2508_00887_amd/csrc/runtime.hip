@@ -66,8 +66,22 @@ constexpr size_t kAlign = 256;
 constexpr size_t kFlagBytes = 8 * 1024;  // >= 8 * (max on-chip grid + 1)
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Tile table set by fram_set_tile_table (an autotuner's choice per size
+// bucket), shared by every context of the process: bucket k covers
+// n_max[k-1] < n <= n_max[k].
+constexpr int kMaxTileBuckets = 64;
+std::mutex g_tile_mu;
+int g_tile_count = 0;
+int g_tile_nmax[kMaxTileBuckets];
+int g_tile_edge[kMaxTileBuckets];
+
 int choose_tile(int n, int requested) {
   if (requested == 64 || requested == 128 || requested == 256) return requested;
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    for (int k = 0; k < g_tile_count; ++k)
+      if (n <= g_tile_nmax[k]) return g_tile_edge[k];
+  }
   const int cands[3] = {256, 128, 64};
   for (int bm : cands) {
     const long nb = (n + bm - 1) / bm;
@@ -867,6 +881,27 @@ void fram_destroy(fram_ctx* c) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
+}
+
+fram_status fram_set_tile_table(const int* n_max, const int* tile, int count) {
+  if (count < 0 || count > kMaxTileBuckets) return FRAM_EINVAL;
+  if (count > 0 && (!n_max || !tile)) return FRAM_EINVAL;
+  for (int k = 0; k < count; ++k) {
+    if (n_max[k] < 1 || (k > 0 && n_max[k] <= n_max[k - 1])) return FRAM_EINVAL;
+    if (tile[k] != 64 && tile[k] != 128 && tile[k] != 256) return FRAM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  for (int k = 0; k < count; ++k) {
+    g_tile_nmax[k] = n_max[k];
+    g_tile_edge[k] = tile[k];
+  }
+  g_tile_count = count;
+  return FRAM_OK;
+}
+
+int fram_auto_tile(int n) {
+  if (n < 1 || n > FRAM_MAX_N) return 0;
+  return choose_tile(n, 0);
 }
 
 size_t fram_workspace_bytes(int n, fram_precision prec, int tile) {

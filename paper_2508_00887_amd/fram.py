@@ -85,6 +85,8 @@ _SIGS = {
     "fram_create": (_I, [ctypes.POINTER(_P), _I, ctypes.c_size_t]),
     "fram_destroy": (None, [_P]),
     "fram_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I]),
+    "fram_set_tile_table": (_I, [_P, _P, _I]),
+    "fram_auto_tile": (_I, [_I]),
     "fram_solve": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P]),
     "fram_solve_ex": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P]),
     "fram_solve_dev": (_I, [_P, _P, _P, _I, _D, _I, _D, _P, _P, _P, _P, _P]),
@@ -133,6 +135,10 @@ def load_library():
         raise ImportError(f"{path}: fram_options / fram_stats are {ob.value} / {sb.value} bytes, "
                           f"the binding expects {ctypes.sizeof(Options)} / {ctypes.sizeof(Stats)}")
     _lib = lib
+    cache = os.environ.get("FRAM_TUNE_CACHE")
+    if cache:
+        from . import tune
+        tune.apply(tune.load(cache))
     return lib
 
 
@@ -169,6 +175,23 @@ def fram_destroy(ctx: int) -> None:
 
 def fram_workspace_bytes(n: int, prec: int = FRAM_FP32, tile: int = 0) -> int:
     return int(load_library().fram_workspace_bytes(n, prec, tile))
+
+
+def fram_set_tile_table(n_max, tile) -> None:
+    """fram_set_tile_table: bucket k covers n_max[k-1] < n <= n_max[k] and
+    selects tile[k]; empty sequences clear the table."""
+    n_max = np.ascontiguousarray(n_max, dtype=np.int32)
+    tile = np.ascontiguousarray(tile, dtype=np.int32)
+    if n_max.shape != tile.shape or n_max.ndim != 1:
+        raise ValueError("n_max and tile must be 1-D sequences of the same length")
+    st = load_library().fram_set_tile_table(_ptr(n_max) if n_max.size else None,
+                                            _ptr(tile) if tile.size else None, int(n_max.size))
+    if st != FRAM_OK:
+        raise FramError(st, "fram_set_tile_table")
+
+
+def fram_auto_tile(n: int) -> int:
+    return int(load_library().fram_auto_tile(n))
 
 
 def fram_status_str(status: int) -> str:
