@@ -1,22 +1,21 @@
 """Continuous-batching request loop for FRAM solves on one GPU.
 
-Requests (graph pairs) arrive over time.  Each is admitted when its device
-workspace fits the HBM budget that is still free, and is solved on one of a
-few worker contexts, each with its own HIP stream and workspace, so the
-kernels of different requests overlap on the device:
+Requests (graph pairs) arrive over time.  A pool of worker slots serves them:
+each slot is a context with its own HIP stream and workspace, so the kernels
+of every request in flight overlap on the device.  A request is admitted the
+moment a slot is free and its device workspace fits the HBM budget that is
+still free; it is never held back for other requests.
 
-* requests with n <= ``small_n`` are gathered by the batching worker, which
-  takes every small request waiting when it becomes free and hands them to
-  fram_solve_many in one call; that call solves the pairs concurrently on its
-  own worker contexts (a stream each), and every pair runs exactly the
-  single-pair solve, so a request's result is the same whether it ran alone
-  or with others;
-* larger requests go to the single-pair workers (fram_solve_ex) with
-  per-pass SDSN launches, which share the device with whatever else runs.
+* requests with n <= ``small_n`` are taken by the small slots, and by a large
+  slot that finds no large request waiting;
+* larger requests are taken by the large slots only, so a burst of large
+  requests cannot hold up the small ones.
 
-Latency is measured from a request's arrival to the moment its result is
-back on the host.  The loop is plain Python around native calls (ctypes
-releases the GIL during each call, so the workers run concurrently).
+Every request runs exactly the single-pair solve (fram_solve_ex), so its
+result is the same whether it ran alone or in the mix.  Latency is measured
+from a request's arrival to the moment its result is back on the host.  The
+loop is plain Python around native calls (ctypes releases the GIL during each
+call, so the slots run concurrently).
 """
 from __future__ import annotations
 
@@ -78,11 +77,12 @@ class Budget:
 
 class Server:
     def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 3,
-                 small_n: int = 512, max_batch: int = 256, prec: str = "bf16",
+                 small_workers: int = 5, small_n: int = 512, prec: str = "bf16",
                  theta: float = 2.0, iters: int = 100, tol: float = 1e-6,
                  stall_iters: int = 3, device: int = 0, context_factory=None):
+        if large_workers < 1 or small_workers < 0:
+            raise ValueError("need at least one large slot and no negative slot count")
         self.small_n = small_n
-        self.max_batch = max_batch
         self.opts = dict(prec=prec, stall_iters=stall_iters)
         self.theta, self.iters, self.tol = theta, iters, tol
         self.budget = Budget(hbm_budget_bytes)
@@ -93,26 +93,23 @@ class Server:
         self.completed: list[Request] = []
         self.t0 = 0.0
         make = context_factory or Context
-        self.ctx_small = make(device)
-        self.ctx_large = [make(device) for _ in range(large_workers)]
-        self.threads = [threading.Thread(target=self._small_loop, daemon=True)]
-        self.threads += [threading.Thread(target=self._large_loop, args=(c, f"large{i}"),
-                                          daemon=True) for i, c in enumerate(self.ctx_large)]
+        self.slots = [(f"small{i}", make(device), False) for i in range(small_workers)]
+        self.slots += [(f"large{i}", make(device), True) for i in range(large_workers)]
+        self.threads = [threading.Thread(target=self._slot_loop, args=(name, c, large),
+                                         daemon=True) for name, c, large in self.slots]
 
     # ------------------------------------------------------------- clock
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
     # ------------------------------------------------------------- bytes
-    def _bytes(self, n: int, batched: bool) -> int:
+    def _bytes(self, n: int) -> int:
         p = PRECISIONS[self.opts["prec"]]
-        np_ = (n + 31) // 32 * 32
-        es = 4 if p == 0 else 2
-        if batched:
-            return 16 * n * n + np_ * np_ * (4 * es + 8) + 8 * n + 4096
         try:
             return fram_workspace_bytes(n, p)
         except (ImportError, OSError):
+            np_ = (n + 31) // 32 * 32
+            es = 4 if p == 0 else 2
             return 16 * n * n + 4 * np_ * np_ * (3 * es + 12)
 
     # ------------------------------------------------------------- API
@@ -132,10 +129,10 @@ class Server:
             self.cv.notify_all()
         for t in self.threads:
             t.join()
-        for c in [self.ctx_small, *self.ctx_large]:
+        for _, c, _ in self.slots:
             c.close()
 
-    # ------------------------------------------------------------- workers
+    # ------------------------------------------------------------- slots
     def _finish(self, req: Request, perm, obj, st, worker: str):
         req.perm, req.objective, req.stats, req.worker = perm, obj, st, worker
         req.done = self.now()
@@ -143,37 +140,24 @@ class Server:
             self.completed.append(req)
             self.cv.notify_all()
 
-    def _small_loop(self):
-        while True:
-            with self.cv:
-                while not self.q_small and not self.stop.is_set():
-                    self.cv.wait(0.01)
-                if self.stop.is_set() and not self.q_small:
-                    return
-                batch = []
-                while self.q_small and len(batch) < self.max_batch:
-                    batch.append(self.q_small.popleft())
-            nbytes = sum(self._bytes(r.n, True) for r in batch)
-            if not self.budget.acquire(nbytes, self.stop):
-                return
-            try:
-                perms, objs, stats = self.ctx_small.solve_many(
-                    [r.A for r in batch], [r.B for r in batch], theta=self.theta,
-                    iters=self.iters, tol=self.tol, **self.opts)
-            finally:
-                self.budget.release(nbytes)
-            for r, p, o, s in zip(batch, perms, objs, stats):
-                self._finish(r, p, o, s, "batched")
+    def _take(self, large: bool) -> Request | None:
+        """Next request for a slot (oldest first), or None once stopped and drained."""
+        with self.cv:
+            while True:
+                if large and self.q_large:
+                    return self.q_large.popleft()
+                if self.q_small:
+                    return self.q_small.popleft()
+                if self.stop.is_set():
+                    return None
+                self.cv.wait(0.01)
 
-    def _large_loop(self, ctx: Context, name: str):
+    def _slot_loop(self, name: str, ctx, large: bool):
         while True:
-            with self.cv:
-                while not self.q_large and not self.stop.is_set():
-                    self.cv.wait(0.01)
-                if self.stop.is_set() and not self.q_large:
-                    return
-                req = self.q_large.popleft()
-            nbytes = self._bytes(req.n, False)
+            req = self._take(large)
+            if req is None:
+                return
+            nbytes = self._bytes(req.n)
             if not self.budget.acquire(nbytes, self.stop):
                 return
             try:
@@ -212,5 +196,5 @@ def summarize(done: list[Request], warmup_s: float, duration_s: float) -> dict:
         mean_ms=float(np.mean(lat)),
         solves_per_s=len(meas) / max(1e-9, last - warmup_s),
         offered_per_s=len(meas) / duration_s,
-        batched=sum(1 for r in meas if r.worker == "batched"),
+        by_small_slots=sum(1 for r in meas if r.worker.startswith("small")),
     )

@@ -1,5 +1,6 @@
-"""Serving loop: admission, batching and overlap logic on the CPU with a fake
-executor; on the GPU, every result must equal the same request solved alone."""
+"""Serving loop: admission, slot routing and overlap logic on the CPU with a
+fake executor; on the GPU, every result must equal the same request solved
+alone."""
 import threading
 import time
 
@@ -39,12 +40,6 @@ class FakeContext:
         p, o = self._answer(A)
         return p, o, {"outer_iters": 1}
 
-    def solve_many(self, As, Bs, **kw):
-        self.calls.append(("many", [a.shape[0] for a in As], kw))
-        self._work(sum(a.shape[0] ** 2 for a in As))
-        out = [self._answer(a) for a in As]
-        return [p for p, _ in out], np.array([o for _, o in out]), [{"outer_iters": 1}] * len(As)
-
     def close(self):
         pass
 
@@ -74,22 +69,40 @@ def test_budget_blocks_until_released():
     assert got == [True] and b.free == 50
 
 
-def test_server_routes_batches_and_completes_everything():
+def test_server_routes_requests_to_slots_and_completes_everything():
     FakeContext.peak = 0
     reqs = _trace(120, 400.0, 1)
-    srv = Server(hbm_budget_bytes=1 << 40, large_workers=2, small_n=256, context_factory=FakeContext)
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=2, small_workers=3, small_n=256,
+                 context_factory=FakeContext)
     done = srv.replay(reqs, timeout_s=60)
     assert len(done) == len(reqs)
     for r in done:
         p, o = FakeContext._answer(r.A)
         np.testing.assert_array_equal(r.perm, p)
         assert r.objective == o and r.done >= r.arrival
-        assert (r.worker == "batched") == (r.n <= 256)
-    many = [c for c in srv.ctx_small.calls if c[0] == "many"]
-    assert any(len(c[1]) > 1 for c in many), "small requests waiting together share a launch"
-    assert FakeContext.peak >= 2, "requests overlap across workers"
+        # large requests only on large slots; small ones on either kind
+        assert r.worker.startswith("large") or r.n <= 256
+    assert {r.worker for r in done if r.n <= 256} & {"small0", "small1", "small2"}
+    # every solve is one single-pair call, with the server's options
+    for _, c, _ in srv.slots:
+        assert all(k == "solve" and kw["sdsn_mode"] == "stream" and kw["prec"] == "bf16"
+                   for k, _, kw in c.calls)
+    assert FakeContext.peak >= 2, "requests overlap across slots"
     s = summarize(done, warmup_s=0.0, duration_s=reqs[-1].arrival)
     assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_a_request_is_admitted_while_another_runs():
+    # A long request occupies one slot; a small one arriving later must finish
+    # first instead of waiting for it.
+    big = np.ones((900, 900))
+    small = np.ones((40, 40))
+    reqs = [Request(rid=0, A=big, B=big, arrival=0.0),
+            Request(rid=1, A=small, B=small, arrival=0.01)]
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=1, small_workers=1, small_n=256,
+                 context_factory=FakeContext)
+    done = {r.rid: r for r in srv.replay(reqs, timeout_s=60)}
+    assert done[1].done < done[0].done
 
 
 def test_admission_respects_budget():
@@ -113,17 +126,13 @@ def test_served_results_equal_solving_alone():
         n = int(round(np.exp(rng.uniform(np.log(30), np.log(900)))))
         pr = synth.make_pair(n, 0.3, 0.05, 4000 * 1000 + i)
         reqs.append(Request(rid=i, A=pr.A, B=pr.B, arrival=t))
-    srv = Server(hbm_budget_bytes=16 << 30, large_workers=3, small_n=512)
+    srv = Server(hbm_budget_bytes=16 << 30, large_workers=3, small_workers=5, small_n=512)
     done = srv.replay(reqs, timeout_s=300)
     assert len(done) == len(reqs)
+    assert len({r.worker for r in done}) >= 2
     with Context(0) as ctx:
         for r in done:
-            if r.worker == "batched":
-                p, o, _ = ctx.solve_many([r.A], [r.B], iters=100, tol=1e-6, prec="bf16",
-                                         stall_iters=3)
-                p, o = p[0], o[0]
-            else:
-                p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stall_iters=3,
-                                    sdsn_mode="stream")
+            p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stall_iters=3,
+                                sdsn_mode="stream")
             np.testing.assert_array_equal(r.perm, p)
             assert r.objective == o
