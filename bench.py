@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="offered requests/s of the served leg (the served workload: 200)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -311,7 +313,7 @@ def main():
         line["batched"] = batched_leg(Context)
     if args.serve:
         log("served leg")
-        line["served"] = served_leg(duration_s=args.serve_seconds)
+        line["served"] = served_leg(rate=args.serve_rate, duration_s=args.serve_seconds)
     if not args.no_cpu_baseline:
         if g is not None:
             T, P, src = g["outer_iters"], int(sum(g["sdsn_passes"])), "the oracle's stored run"
