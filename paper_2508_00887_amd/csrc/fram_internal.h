@@ -67,6 +67,12 @@ hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C,
 hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, int n, int np,
                              Partials out, DevState* st, hipStream_t s);
 
+// Passes k_first .. k_last of a projection whose padded matrix is one tile
+// (np == bm), in a single workgroup launch; p0 / p1 are the partial buffers of
+// even / odd pass parity (pass k reads parity k - 1, writes parity k).
+hipError_t launch_sdsn_chunk(int bm, float* X, int n, int np, Partials p0, Partials p1,
+                             DevState* st, int k_first, int k_last, int max_passes, double theta,
+                             double gamma_tol, hipStream_t s, double fixed_scale = 0.0);
 // One SDSN pass (Algorithm 2 body) over X in place, pass index k >= 1.  Reads
 // the partials of its input from `in`, writes those of its output to `out`.
 hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,

@@ -361,7 +361,22 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
     }
     k = last + 1;
   }
-  while (o.profile != 1) {
+  if (L.nb == 1 && o.profile != 1) {
+    // A single tile: the whole projection is one workgroup launch.
+    Prof p{o.profile, c, s, 0.0f};
+    fram_status r0 = timed(p, &stt->ms_sdsn, nullptr, [&] {
+      return fram::launch_sdsn_chunk(L.bm, X, n, L.np, partials(c, L, 0), partials(c, L, 1), st,
+                                     1, last, o.sdsn_max, theta, o.gamma_tol, s, fixed_scale);
+    });
+    if (r0 != FRAM_OK) return r0;
+    fram_status r = read_state(c, st, s);
+    if (r != FRAM_OK) return r;
+    if (!c->hst->done) {
+      c->err = "SDSN loop ended without completion flag";
+      return FRAM_EDEVICE;
+    }
+  }
+  while (o.profile != 1 && L.nb != 1) {
     const int end = std::min(last, k + chunk - 1);
     Prof p{o.profile, c, s, 0.0f};
     fram_status r0 = timed(p, &stt->ms_sdsn, nullptr, [&] {

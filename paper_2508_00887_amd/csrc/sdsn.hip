@@ -45,9 +45,11 @@ struct TileArgs {
 };
 
 // PASS = false: statistics of src (and optional padded copy into dst).
-// PASS = true : one SDSN pass, in place on dst (== src, ld np).
+// PASS = true : one SDSN pass, in place on dst (== src, ld np); returns true
+// when the projection is complete (this pass found it done or marked it), the
+// same value in every thread of the workgroup.
 template <int BM, bool PASS>
-__global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
+__device__ __forceinline__ bool tile_body(const TileArgs& a) {
   constexpr int NT = TileShape<BM>::NT;
   constexpr int LPR = TileShape<BM>::LPR;      // lanes per tile row
   constexpr int RPW = TileShape<BM>::RPW;      // tile rows per wave step
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     s_chain[1][p][r] = csum;
     if (tid == 0) s_done = done;
     const double S = block_sum<NT>(part, s_red);  // its barriers publish s_done, s_chain
-    if (s_done) return;
+    if (s_done) return true;
     if (a.k >= 2) {
       const double gamma_in = S / n - 1.0;
       if (gamma_in <= a.gamma_tol || a.k > a.max_passes) {
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
           st->passes = a.k - 1;
           st->gamma = gamma_in;
         }
-        return;
+        return true;
       }
     } else {
       m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
@@ -196,6 +198,29 @@ __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
     const float tm = block_max<NT>(lmax, reinterpret_cast<float*>(s_red));
     if (tid == 0) a.out.tmax[bm * nb + bn] = tm;
   }
+  return false;
+}
+
+template <int BM, bool PASS>
+__global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
+  (void)tile_body<BM, PASS>(a);
+}
+
+// Passes a.k .. k_last of a projection whose matrix is a single tile, in one
+// workgroup: pass k + 1 reads the partial sums that pass k wrote, which the
+// workgroup barrier between them makes visible, so no launch (and no host
+// round trip) separates the passes.  Stops at the pass that completes the
+// projection, exactly where the per-pass launches would.
+template <int BM>
+__global__ __launch_bounds__(4 * BM) void tile_chunk_kernel(TileArgs a, Partials p0, Partials p1,
+                                                            int k_last) {
+  for (int k = a.k; k <= k_last; ++k) {
+    a.k = k;
+    a.in = ((k - 1) & 1) ? p1 : p0;
+    a.out = (k & 1) ? p1 : p0;
+    if (tile_body<BM, true>(a)) break;
+    __syncthreads();
+  }
 }
 
 template <bool PASS>
@@ -232,6 +257,39 @@ hipError_t launch_tile_stats(int bm, const float* src, int ld_src, float* dst, i
   a.out = out;
   a.st = st;
   return launch_tile<false>(bm, a, s);
+}
+
+hipError_t launch_sdsn_chunk(int bm, float* X, int n, int np, Partials p0, Partials p1,
+                             DevState* st, int k_first, int k_last, int max_passes, double theta,
+                             double gamma_tol, hipStream_t s, double fixed_scale) {
+  if (np != bm || n > np || n < 1 || k_first < 1 || k_last < k_first) return hipErrorInvalidValue;
+  TileArgs a{};
+  a.src = X;
+  a.ld_src = np;
+  a.dst = X;
+  a.n = n;
+  a.np = np;
+  a.st = st;
+  a.k = k_first;
+  a.max_passes = max_passes;
+  a.theta = theta;
+  a.gamma_tol = gamma_tol;
+  a.fixed_scale = fixed_scale;
+  const dim3 one(1, 1);
+  switch (bm) {
+    case 64:
+      tile_chunk_kernel<64><<<one, dim3(256), 0, s>>>(a, p0, p1, k_last);
+      break;
+    case 128:
+      tile_chunk_kernel<128><<<one, dim3(512), 0, s>>>(a, p0, p1, k_last);
+      break;
+    case 256:
+      tile_chunk_kernel<256><<<one, dim3(1024), 0, s>>>(a, p0, p1, k_last);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partials out,
