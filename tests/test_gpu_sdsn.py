@@ -98,6 +98,22 @@ def test_sdsn_tile_variants_agree(ctx, tile):
     np.testing.assert_allclose(Xa, Xb, atol=1e-6)
 
 
+@pytest.mark.parametrize("n,tile", [(1, 64), (37, 64), (64, 64), (100, 128), (200, 256)])
+def test_single_tile_launch_equals_per_pass_launches(ctx, n, tile):
+    # A matrix that is one tile runs the whole projection in one launch; with
+    # profile = 1 every pass is its own launch.  Same passes, same arithmetic.
+    K = (np.random.default_rng(90 + n).random((n, n)) ** 2).astype(np.float32)
+    X1, s1 = ctx.sdsn_project(K, 2.0, tile=tile, sdsn_mode="stream")
+    X2, s2 = ctx.sdsn_project(K, 2.0, tile=tile, sdsn_mode="stream", profile=True)
+    assert s1["sdsn_passes"] == s2["sdsn_passes"] and s1["gamma"] == s2["gamma"]
+    np.testing.assert_array_equal(X1, X2)
+    # and a cap that stops the loop early is honoured exactly
+    X3, s3 = ctx.sdsn_project(K, 2.0, tile=tile, sdsn_mode="stream", sdsn_max=3)
+    X4, s4 = ctx.sdsn_project(K, 2.0, tile=tile, sdsn_mode="stream", sdsn_max=3, profile=True)
+    assert s3["sdsn_passes"] == s4["sdsn_passes"] <= 3
+    np.testing.assert_array_equal(X3, X4)
+
+
 @pytest.mark.parametrize("n", [3, 65, 300, 1000, 2100, 4000])
 def test_onchip_equals_streaming_bitwise(ctx, n):
     # Same formulas and the same fixed reduction order per tile: the on-chip
