@@ -162,8 +162,9 @@ size_t fram_workspace_bytes(int n, fram_precision prec, int tile);
  * square tile edge of the SDSN passes and GEMMs of a solve or projection of
  * size n.  Bucket k covers n_max[k-1] < n <= n_max[k] (n_max strictly
  * increasing, >= 1) and selects tile[k] (64, 128 or 256); sizes above the
- * last bucket keep the built-in rule (the largest tile whose grid has at
- * least 200 tiles, else 64).  The table is copied; it is shared by every
+ * last bucket keep the built-in rule (one tile up to n = 128: 64 for
+ * n <= 64, else 128; above, the largest tile whose grid has at least 200
+ * tiles, else 64).  The table is copied; it is shared by every
  * context of the process and also governs fram_workspace_bytes(.., 0).
  * count == 0 clears it.  At most 64 buckets.  Returns FRAM_EINVAL (table
  * unchanged) on a count out of range, a NULL array with count > 0, an

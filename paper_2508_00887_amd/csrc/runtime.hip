@@ -82,6 +82,9 @@ int choose_tile(int n, int requested) {
     for (int k = 0; k < g_tile_count; ++k)
       if (n <= g_tile_nmax[k]) return g_tile_edge[k];
   }
+  // Up to 128 the matrix is one tile and a projection is one launch.
+  if (n <= 64) return 64;
+  if (n <= 128) return 128;
   const int cands[3] = {256, 128, 64};
   for (int bm : cands) {
     const long nb = (n + bm - 1) / bm;

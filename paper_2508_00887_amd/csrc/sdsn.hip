@@ -48,7 +48,11 @@ struct TileArgs {
 // PASS = true : one SDSN pass, in place on dst (== src, ld np); returns true
 // when the projection is complete (this pass found it done or marked it), the
 // same value in every thread of the workgroup.
-template <int BM, bool PASS>
+// WHOLE (passes only, for a matrix that is one padded tile): every row of the
+// wave is read before the first is written, so a pass costs one memory round
+// trip instead of one per row; rows and columns past n are read (zero
+// padding) and written back as zeros.
+template <int BM, bool PASS, bool WHOLE = false>
 __device__ __forceinline__ bool tile_body(const TileArgs& a) {
   constexpr int NT = TileShape<BM>::NT;
   constexpr int LPR = TileShape<BM>::LPR;      // lanes per tile row
@@ -156,6 +160,26 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
   float lmax = -INFINITY;
   const bool c0 = j < n, c1 = j + 1 < n, c2 = j + 2 < n, c3 = j + 3 < n;
 
+  if constexpr (PASS && WHOLE) {
+    float4 xv[STEPS];
+#pragma unroll
+    for (int stp = 0; stp < STEPS; ++stp)
+      xv[stp] = *reinterpret_cast<const float4*>(a.dst + (size_t)(w * 16 + stp * RPW + q) * np + j);
+#pragma unroll
+    for (int stp = 0; stp < STEPS; ++stp) {
+      const int rl = w * 16 + stp * RPW + q;
+      const bool in = rl < n;
+      const float ai = s_a[rl];
+      const float4 x = xv[stp];
+      float4 y;
+      y.x = (in && c0) ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
+      y.y = (in && c1) ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
+      y.z = (in && c2) ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
+      y.w = (in && c3) ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
+      *reinterpret_cast<float4*>(a.dst + (size_t)rl * np + j) = y;
+      tile_step_sums<BM>(y, rl, s_rowsum, cacc);
+    }
+  } else {
 #pragma unroll
   for (int stp = 0; stp < STEPS; ++stp) {
     const int rl = w * 16 + stp * RPW + q;
@@ -192,6 +216,7 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
     }
     tile_step_sums<BM>(y, rl, s_rowsum, cacc);
   }
+  }
   tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.out.rowp, a.out.colp, a.out.tot, bm, bn,
                     nb, np);
   if (!PASS) {
@@ -218,7 +243,9 @@ __global__ __launch_bounds__(4 * BM) void tile_chunk_kernel(TileArgs a, Partials
     a.k = k;
     a.in = ((k - 1) & 1) ? p1 : p0;
     a.out = (k & 1) ? p1 : p0;
-    if (tile_body<BM, true>(a)) break;
+    // Whole-tile loads pay off while the wave's rows fit in registers next to
+    // everything else (BM <= 128); at 256 they spill.
+    if (tile_body<BM, true, (BM <= 128)>(a)) break;
     __syncthreads();
   }
 }

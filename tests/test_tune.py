@@ -24,9 +24,10 @@ def table():
 
 def test_builtin_rule_without_a_table(table):
     tune.clear()
-    # the largest edge whose grid has at least 200 tiles, else 64
-    assert [F.fram_auto_tile(n) for n in (1, 500, 1000, 1700, 1800, 3500, 3600, 4000, 32768)] == \
-        [64, 64, 64, 64, 128, 128, 256, 256, 256]
+    # one tile up to 128, then the largest edge whose grid has at least 200 tiles, else 64
+    assert [F.fram_auto_tile(n) for n in (1, 64, 65, 128, 129, 500, 1000, 1700, 1800, 3500, 3600,
+                                          4000, 32768)] == \
+        [64, 64, 128, 128, 64, 64, 64, 64, 128, 128, 256, 256, 256]
     assert F.fram_auto_tile(0) == 0 and F.fram_auto_tile(32769) == 0
 
 
@@ -40,7 +41,7 @@ def test_table_selects_per_bucket_then_falls_back(table):
         t = F.fram_auto_tile(n)
         assert F.fram_workspace_bytes(n, F.FRAM_BF16, 0) == F.fram_workspace_bytes(n, F.FRAM_BF16, t)
     tune.clear()
-    assert F.fram_auto_tile(100) == 64
+    assert F.fram_auto_tile(100) == 128 and F.fram_auto_tile(200) == 64
 
 
 @pytest.mark.parametrize("n_max,tile", [
