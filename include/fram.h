@@ -98,6 +98,8 @@ typedef struct {
   double ms_update;      /* N update + delta                                           */
   int stalled;           /* 1 if the delta-stall rule (fram_options.stall_iters) stopped
                             the loop                                                   */
+  double ms_discretize;  /* (profile 1 or 2) Algorithm 1 step 10 on the device: row
+                            argmax, column minima and the exact assignment           */
 } fram_stats;
 
 typedef struct {
@@ -112,10 +114,11 @@ typedef struct {
                             permutation for w consecutive iterations (a second stop
                             rule beside delta <= tol, for precisions whose delta
                             levels off above tol); 0 = off (default)                 */
-  int sdsn_mode;         /* 0 = automatic, 1 = one streaming launch per SDSN pass,
-                            2 = on-chip: all passes of a projection in one cooperative
-                            launch with the iterate held in registers (FRAM_EINVAL if
-                            the device cannot hold it)                                */
+  int sdsn_mode;         /* 0 = automatic (currently the streaming passes), 1 = one
+                            streaming launch per SDSN pass, 2 = on-chip: all passes of
+                            a projection in one cooperative launch with the iterate
+                            held in registers (FRAM_EINVAL if the device cannot hold
+                            it; fram_sdsn_project only)                               */
   int stall_iters;       /* w > 0: also stop once delta has stalled at the precision's
                             floor: after delta <= stall_delta, w consecutive iterations
                             without a new smallest delta; 0 = off (default)            */
@@ -134,6 +137,18 @@ typedef struct {
                             1..32, default 8.  Measured on 512 pairs of n in [20, 300]:
                             8 workers 90 pairs/s, 4 workers 83; with the default 4
                             hardware queues per process (more queues were slower)     */
+  const float* N0;       /* warm start of Algorithm 1 step 1: NULL (default) starts from
+                            N = 0; else n*n floats, row-major, finite, used as N^(0)
+                            (host memory for the host entry points, device memory with
+                            leading dimension n for the _dev ones).  A solve of a + b
+                            fixed iterations (tol = 0) equals, bit for bit, a solve of a
+                            iterations whose N_out is passed as N0 to a solve of b: the
+                            iterate is the whole state of the loop (the stop-rule
+                            counters of stall_iters / stable_iters restart with the
+                            call).  Single-pair solves only (fram_solve_many: EINVAL). */
+  float* N_out;          /* NULL (default) or n*n floats (same memory kind as N0): the
+                            final iterate N, before discretisation (not written for
+                            n = 1, which needs no iteration)                          */
 } fram_options;
 
 /* Sizes of fram_options and fram_stats as compiled into the library, for
@@ -261,14 +276,16 @@ fram_status fram_solve_attr_dev(fram_ctx* ctx, const double* dA, const double* d
 /* Exact linear assignment of Algorithm 1 step 10 / eq. (2), the discretisation
  * the paper does with the Hungarian method (Sec. 6): perm_out maximises
  * sum_i W[i, perm_out[i]], i.e. it is the permutation P minimising ||P - W||_F.
- * Runs on the device: row maxima as the starting duals, then one shortest
- * augmenting path (with row/column potentials) per row whose maximum collides
- * with a lower-numbered row's; when the row argmax is already a permutation
- * it is returned as is.  Ties go to the lowest column.  The solvers use the
- * same device code for their final step.
+ * Runs on the device in three phases: row maxima as the starting duals and
+ * column minima of the reduced costs as the starting prices; two passes of
+ * Jonker-Volgenant augmenting row reduction (bids of the free rows, at most
+ * 4 * free + n / 2 of them); then one shortest augmenting path (with row and
+ * column potentials) per row still free.  When the row argmax is already a
+ * permutation it is returned as is.  Ties go to the lowest column.  The
+ * solvers use the same device code for their final step.
  *   W        host, n*n floats, row-major, finite (else FRAM_EINVAL).
  *   perm_out host, n int32 (written).
- * fram_last_stats().lap_paths reports the augmenting paths taken. */
+ * fram_last_stats().lap_paths reports the rows the row argmax left free. */
 fram_status fram_assign(fram_ctx* ctx, const float* W, int n, int32_t* perm_out);
 
 /* Same on device memory: dW n x n floats with leading dimension ldw >= n,
@@ -278,13 +295,16 @@ fram_status fram_assign(fram_ctx* ctx, const float* W, int n, int32_t* perm_out)
 fram_status fram_assign_dev(fram_ctx* ctx, const float* dW, int ldw, int n, int32_t* dperm,
                             void* stream);
 
-/* Many independent pairs (uneven n) solved in one batched device launch.
+/* Many independent pairs (uneven n), each solved as by fram_solve_ex.
  *   count        >= 1 pairs; A[i], B[i] host n[i]*n[i] doubles.
  *   perm_out[i]  host, n[i] int32 (written); objective_out host, count doubles.
- *   opt          NULL = defaults (FRAM_BF16 GEMMs for the batched kernel).
+ *   opt          NULL = defaults; opt->N0 / opt->N_out must be NULL.
  *   stats        NULL or count entries.
- * Each pair's result is computed exactly as by the batched kernel alone:
- * batching never changes a pair's arithmetic. */
+ * The pairs are spread over worker contexts of ctx (opt->many_workers of
+ * them, each with its own stream, workspace and host thread), every pair
+ * running the single-pair solve on its worker, so a pair's result is the
+ * same as when it is solved alone.  The first error stops the call and is
+ * returned (later pairs are then left unwritten). */
 fram_status fram_solve_many(fram_ctx* ctx, int count, const double* const* A,
                             const double* const* B, const int* n, double lambda, int iters,
                             double tol, int32_t* const* perm_out, double* objective_out);
@@ -294,6 +314,16 @@ fram_status fram_solve_many_ex(fram_ctx* ctx, int count, const double* const* A,
                                int iters, double tol, const fram_options* opt,
                                int32_t* const* perm_out, double* objective_out,
                                fram_stats* stats);
+
+/* Device memory the context holds between calls: its workspace (which only
+ * grows, to the largest problem solved so far), that of its fram_solve_many
+ * workers, and its small fixed buffers.  Pure host bookkeeping. */
+size_t fram_resident_bytes(const fram_ctx* ctx);
+
+/* Release the workspace of the context and of its workers (after waiting for
+ * their streams); the next call allocates again.  For admission control that
+ * must bound the memory held by idle contexts.  NULL is accepted. */
+fram_status fram_trim(fram_ctx* ctx);
 
 /* Stats of the last call on this context. */
 fram_status fram_last_stats(const fram_ctx* ctx, fram_stats* out);

@@ -193,6 +193,14 @@ fram_status check_scalars(int n, double theta, int iters, double tol) {
   return FRAM_OK;
 }
 
+// A host warm start must be finite.
+fram_status check_warm(const fram_options& o, int n) {
+  if (o.N0 == nullptr) return FRAM_OK;
+  for (size_t t = 0; t < (size_t)n * n; ++t)
+    if (!std::isfinite(o.N0[t])) return FRAM_EINVAL;
+  return FRAM_OK;
+}
+
 // Sec. 3: A is nonnegative and symmetric; entries must also be finite.
 fram_status check_graph(const double* A, int n) {
   for (int i = 0; i < n; ++i)
@@ -415,7 +423,8 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
 // Decide whether the on-chip SDSN path is used for this layout.
 fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool* on) {
   *on = false;
-  if (o.sdsn_mode == 1) return FRAM_OK;
+  // Automatic mode streams: the on-chip launch is taken only when asked for.
+  if (o.sdsn_mode != 2) return FRAM_OK;
   if (o.sdsn_max > (1 << 24) - 8) {  // barrier epochs of one launch must stay below 2^24
     if (o.sdsn_mode == 2) {
       c->err = "sdsn_max too large for the on-chip SDSN path";
@@ -498,14 +507,18 @@ struct NodeTerm {
 fram_status finish_discretise(fram_ctx* c, const Layout& L, int n, const double* dA,
                               const double* dB, const NodeTerm& nt, float* N, int32_t* dsig,
                               DevState* st, hipStream_t s, int32_t* perm, double* obj,
-                              int* lap_paths) {
+                              int* lap_paths, Prof& prof, fram_stats* stt) {
   // Row argmax of N with the starting duals, then the exact assignment on the
   // device (nothing to augment when the argmax is a permutation).
   char* lws = at<char>(c, L.lap);
   double* u = reinterpret_cast<double*>(lws);
-  HIPCHK(fram::launch_row_argmax(N, n, L.np, dsig, s, u));
-  fram::LapProblem lp{N, n, L.np, dsig, lws, u, 1, &st->lap_paths};
-  HIPCHK(fram::launch_lap(&lp, nullptr, 1, n, s));
+  fram_status q = timed(prof, &stt->ms_discretize, nullptr, [&] {
+    hipError_t e = fram::launch_row_argmax(N, n, L.np, dsig, s, u);
+    if (e != hipSuccess) return e;
+    fram::LapProblem lp{N, n, L.np, dsig, lws, u, 1, &st->lap_paths};
+    return fram::launch_lap(&lp, nullptr, 1, n, s);
+  });
+  if (q != FRAM_OK) return q;
   HIPCHK(fram::launch_objective(dA, dB, dsig, n, at<double>(c, L.obj), L.nobj, st, s));
   if (nt.K != nullptr) HIPCHK(fram::launch_node_objective(nt.K, dsig, n, nt.w, st, s));
   HIPCHK(hipMemcpyAsync(perm, dsig, (size_t)n * 4, hipMemcpyDeviceToHost, s));
@@ -573,9 +586,21 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     Kp = at<float>(c, L.Kp);
     HIPCHK(fram::launch_node_term(nt.K, n, nt.w, Kp, L.np, at<double>(c, L.mx), L.nmax, st, s));
   }
-  // Algorithm 1, step 1: N^(0) = 0.
+  // Algorithm 1, step 1: N^(0) = 0, or the caller's warm start N0 (n x n,
+  // ld n, host or device memory) with zero padding.
   HIPCHK(fram::launch_zero(N, np2 * 4, s));
-  if (e != Elem::F32) HIPCHK(fram::launch_zero(Nlp, np2 * fram::elem_size(e), s));
+  if (o.N0 != nullptr) {
+    HIPCHK(hipMemcpy2DAsync(N, (size_t)L.np * 4, o.N0, (size_t)n * 4, (size_t)n * 4, n,
+                            hipMemcpyDefault, s));
+    if (e != Elem::F32) {
+      // The GEMM-type copy is cast from a contiguous copy (X is free here),
+      // with the same rounding the update kernel uses.
+      HIPCHK(hipMemcpyAsync(X, o.N0, (size_t)n * n * 4, hipMemcpyDefault, s));
+      HIPCHK(fram::launch_cast_f32(e, X, n, Nlp, L.np, s));
+    }
+  } else if (e != Elem::F32) {
+    HIPCHK(fram::launch_zero(Nlp, np2 * fram::elem_size(e), s));
+  }
 
   // DSPFP variant (Sec. 4, eq. iter.DSPFP): the same outer loop, but the
   // projection is the plain alternating one on the gradient itself (first
@@ -724,8 +749,12 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     }
   }
   if (it > iters) it = iters;
+  if (o.N_out != nullptr)
+    HIPCHK(hipMemcpy2DAsync(o.N_out, (size_t)n * 4, N, (size_t)L.np * 4, (size_t)n * 4, n,
+                            hipMemcpyDefault, s));
   int lap_paths = 0;
-  fram_status r = finish_discretise(c, L, n, dA, dB, nt, N, dsig, st, s, perm, obj, &lap_paths);
+  fram_status r = finish_discretise(c, L, n, dA, dB, nt, N, dsig, st, s, perm, obj, &lap_paths,
+                                    prof, stt);
   if (r != FRAM_OK) return r;
   r = flush_timings(c);
   if (r != FRAM_OK) return r;
@@ -872,6 +901,8 @@ void fram_default_options(fram_options* opt) {
   opt->variant = 0;
   opt->dsn_iters = 30;
   opt->many_workers = 8;
+  opt->N0 = nullptr;
+  opt->N_out = nullptr;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -899,6 +930,29 @@ void fram_destroy(fram_ctx* c) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
+}
+
+size_t fram_resident_bytes(const fram_ctx* c) {
+  if (!c) return 0;
+  size_t b = c->ws_bytes + (c->flags ? kFlagBytes : 0);
+  for (const fram_ctx* w : c->workers) b += fram_resident_bytes(w);
+  return b;
+}
+
+fram_status fram_trim(fram_ctx* c) {
+  if (!c) return FRAM_OK;
+  for (fram_ctx* w : c->workers) {
+    const fram_status r = fram_trim(w);
+    if (r != FRAM_OK) return r;
+  }
+  if (c->ws) {
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  return FRAM_OK;
 }
 
 fram_status fram_set_tile_table(const int* n_max, const int* tile, int count) {
@@ -936,6 +990,7 @@ fram_status fram_solve_ex(fram_ctx* c, const double* A, const double* B, int n, 
   if (r == FRAM_OK) r = check_scalars(n, lambda, iters, tol);
   if (r == FRAM_OK) r = check_graph(A, n);
   if (r == FRAM_OK) r = check_graph(B, n);
+  if (r == FRAM_OK) r = check_warm(o, n);
   if (r != FRAM_OK) {
     c->err = "invalid argument";
     return r;
@@ -984,6 +1039,7 @@ fram_status fram_solve_attr_ex(fram_ctx* c, const double* A, const double* B, co
   if (r == FRAM_OK && !std::isfinite(node_weight)) r = FRAM_EINVAL;
   for (size_t t = 0; r == FRAM_OK && t < (size_t)n * n; ++t)
     if (!std::isfinite(K[t])) r = FRAM_EINVAL;
+  if (r == FRAM_OK) r = check_warm(o, n);
   if (r != FRAM_OK) {
     c->err = "invalid argument";
     return r;
@@ -1312,6 +1368,10 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
   if (!opt) o.prec = FRAM_BF16;
   fram_status r = check_options(o);
   if (r != FRAM_OK) return r;
+  if (o.N0 != nullptr || o.N_out != nullptr) {
+    c->err = "fram_solve_many takes no warm start or final iterate";
+    return FRAM_EINVAL;
+  }
   for (int p = 0; p < count; ++p) {
     if (!A[p] || !B[p] || !perm_out[p]) return FRAM_EINVAL;
     r = check_scalars(n[p], lambda, iters, tol);

@@ -44,6 +44,7 @@ class Stats(ctypes.Structure):
         ("ms_stats", ctypes.c_double),
         ("ms_update", ctypes.c_double),
         ("stalled", ctypes.c_int),
+        ("ms_discretize", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -65,6 +66,8 @@ class Options(ctypes.Structure):
         ("variant", ctypes.c_int),
         ("dsn_iters", ctypes.c_int),
         ("many_workers", ctypes.c_int),
+        ("N0", ctypes.c_void_p),
+        ("N_out", ctypes.c_void_p),
     ]
 
 
@@ -100,6 +103,8 @@ _SIGS = {
     "fram_assign_dev": (_I, [_P, _P, _I, _I, _P, _P]),
     "fram_solve_many": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P]),
     "fram_solve_many_ex": (_I, [_P, _I, _P, _P, _P, _D, _I, _D, _P, _P, _P, _P]),
+    "fram_resident_bytes": (ctypes.c_size_t, [_P]),
+    "fram_trim": (_I, [_P]),
     "fram_last_stats": (_I, [_P, _P]),
     "fram_status_str": (ctypes.c_char_p, [_I]),
     "fram_last_error": (ctypes.c_char_p, [_P]),
@@ -258,15 +263,25 @@ class Context:
             pass
 
     # ------------------------------------------------------------ FRAM
-    def solve(self, A, B, theta=2.0, iters=100, tol=0.0, K=None, node_weight=1.0, **opts):
+    def solve(self, A, B, theta=2.0, iters=100, tol=0.0, K=None, node_weight=1.0, N0=None,
+              N_out=None, **opts):
         """fram_solve_ex (or fram_solve_attr_ex when node similarities K are
-        given) on host arrays; returns (perm, objective, stats dict)."""
+        given) on host arrays; returns (perm, objective, stats dict).  N0: warm
+        start (n x n); N_out: an n x n float32 C-contiguous array that receives
+        the final iterate."""
         A, B = _f64(A), _f64(B)
         n = A.shape[0]
         perm = np.empty(n, dtype=np.int32)
         obj = ctypes.c_double()
         stats = Stats()
         o = _options(**opts)
+        if N0 is not None:
+            N0 = _f32(N0)
+            o.N0 = _ptr(N0)
+        if N_out is not None:
+            if N_out.dtype != np.float32 or not N_out.flags.c_contiguous or N_out.shape != (n, n):
+                raise ValueError("N_out must be a C-contiguous n x n float32 array")
+            o.N_out = _ptr(N_out)
         if K is None:
             st = self.lib.fram_solve_ex(self.handle, _ptr(A), _ptr(B), n, theta, iters, tol,
                                         ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
@@ -281,13 +296,15 @@ class Context:
         return perm.astype(np.int64), obj.value, stats.as_dict()
 
     def solve_dev(self, dA: int, dB: int, n: int, theta=2.0, iters=100, tol=0.0, stream=0,
-                  dK: int = 0, node_weight=1.0, **opts):
+                  dK: int = 0, node_weight=1.0, dN0: int = 0, dN_out: int = 0, **opts):
         """fram_solve_dev (fram_solve_attr_dev with dK) on device pointers
-        (n*n doubles each)."""
+        (n*n doubles each; dN0 / dN_out: n*n floats, or 0)."""
         perm = np.empty(n, dtype=np.int32)
         obj = ctypes.c_double()
         stats = Stats()
         o = _options(**opts)
+        o.N0 = dN0 or None
+        o.N_out = dN_out or None
         if not dK:
             st = self.lib.fram_solve_dev(self.handle, dA, dB, n, theta, iters, tol,
                                          ctypes.byref(o), _ptr(perm), ctypes.byref(obj),
@@ -365,6 +382,14 @@ class Context:
                                          ctypes.byref(o), pp, _ptr(objs), stats)
         _check(self.handle, st, "fram_solve_many_ex")
         return [p.astype(np.int64) for p in perms], objs, [s.as_dict() for s in stats]
+
+    def resident_bytes(self) -> int:
+        """fram_resident_bytes: device memory this context holds between calls."""
+        return int(self.lib.fram_resident_bytes(self.handle))
+
+    def trim(self) -> None:
+        """fram_trim: release the context's device workspace."""
+        _check(self.handle, self.lib.fram_trim(self.handle), "fram_trim")
 
     def last_stats(self) -> dict:
         s = Stats()

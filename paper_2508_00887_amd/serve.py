@@ -16,6 +16,17 @@ result is the same whether it ran alone or in the mix.  Latency is measured
 from a request's arrival to the moment its result is back on the host.  The
 loop is plain Python around native calls (ctypes releases the GIL during each
 call, so the slots run concurrently).
+
+HBM budget.  A context keeps its workspace between calls (it only grows), so
+the budget charges every slot for the memory its context holds, not only for
+the request it runs: before a solve the slot's charge is raised to the
+workspace the request needs (if the budget has room; otherwise the slot
+releases its own workspace and waits for the full amount), and while any
+slot waits for memory, idle slots release theirs (fram_trim).  The memory all
+contexts hold therefore never exceeds the budget.
+
+A request whose solve raises is completed with the error recorded
+(``Request.error``); its slot keeps serving.
 """
 from __future__ import annotations
 
@@ -40,6 +51,7 @@ class Request:
     objective: float = float("nan")
     stats: dict | None = None
     worker: str = ""
+    error: str = ""
 
     @property
     def n(self) -> int:
@@ -51,27 +63,41 @@ class Request:
 
 
 class Budget:
-    """HBM admission: a counting semaphore over bytes."""
+    """HBM admission: a counting semaphore over bytes, with a count of the
+    slots waiting for memory (idle slots release theirs while it is > 0)."""
 
     def __init__(self, total: int):
         self.total = int(total)
         self.free = int(total)
+        self.waiting = 0
         self.cv = threading.Condition()
 
+    def try_acquire(self, nbytes: int) -> bool:
+        with self.cv:
+            if self.free >= nbytes:
+                self.free -= nbytes
+                return True
+            return False
+
     def acquire(self, nbytes: int, stop: threading.Event) -> bool:
+        """Blocks until nbytes are free; nbytes above the total are admitted
+        alone (the whole budget is taken)."""
         nbytes = min(int(nbytes), self.total)
         with self.cv:
-            while self.free < nbytes and not stop.is_set():
-                self.cv.wait(0.01)
-            if stop.is_set():
-                return False
-            self.free -= nbytes
-            return True
+            self.waiting += 1
+            try:
+                while self.free < nbytes and not stop.is_set():
+                    self.cv.wait(0.01)
+                if stop.is_set():
+                    return False
+                self.free -= nbytes
+                return True
+            finally:
+                self.waiting -= 1
 
     def release(self, nbytes: int):
-        nbytes = min(int(nbytes), self.total)
         with self.cv:
-            self.free += nbytes
+            self.free += int(nbytes)
             self.cv.notify_all()
 
 
@@ -140,8 +166,10 @@ class Server:
             self.completed.append(req)
             self.cv.notify_all()
 
-    def _take(self, large: bool) -> Request | None:
-        """Next request for a slot (oldest first), or None once stopped and drained."""
+    def _take(self, large: bool, slot: dict) -> Request | None:
+        """Next request for a slot (oldest first), or None once stopped and
+        drained.  While waiting, an idle slot gives its workspace back if
+        another slot is waiting for memory."""
         with self.cv:
             while True:
                 if large and self.q_large:
@@ -150,22 +178,77 @@ class Server:
                     return self.q_small.popleft()
                 if self.stop.is_set():
                     return None
+                if self.budget.waiting and slot["held"] > self.FIXED:
+                    self.cv.release()
+                    try:
+                        self._trim(slot)
+                    finally:
+                        self.cv.acquire()
+                    continue
                 self.cv.wait(0.01)
 
+    # Device memory a context holds besides its workspace (small fixed
+    # buffers), charged to every slot from its first solve on.
+    FIXED = 1 << 20
+
+    def _trim(self, slot: dict):
+        """Release the slot's workspace and its charge (down to FIXED)."""
+        trim = getattr(slot["ctx"], "trim", None)
+        if trim is not None:
+            trim()
+        if slot["held"] > self.FIXED:
+            self.budget.release(slot["held"] - self.FIXED)
+            slot["held"] = self.FIXED
+
+    def _reserve(self, slot: dict, need: int) -> bool:
+        """Raise the slot's charge to cover `need` bytes of workspace."""
+        want = need + self.FIXED
+        extra = want - slot["held"]
+        if extra <= 0:
+            return True
+        if self.budget.try_acquire(extra):
+            slot["held"] = want
+            return True
+        # Not enough room: give back this slot's own workspace, then wait for
+        # the whole amount (idle slots release theirs meanwhile).
+        self._trim(slot)
+        if slot["held"]:
+            self.budget.release(slot["held"])
+            slot["held"] = 0
+        if not self.budget.acquire(want, self.stop):
+            return False
+        slot["held"] = want
+        return True
+
     def _slot_loop(self, name: str, ctx, large: bool):
-        while True:
-            req = self._take(large)
-            if req is None:
-                return
-            nbytes = self._bytes(req.n)
-            if not self.budget.acquire(nbytes, self.stop):
-                return
-            try:
-                perm, obj, st = ctx.solve(req.A, req.B, theta=self.theta, iters=self.iters,
-                                          tol=self.tol, sdsn_mode="stream", **self.opts)
-            finally:
-                self.budget.release(nbytes)
-            self._finish(req, perm, obj, st, name)
+        slot = {"ctx": ctx, "held": 0}
+        try:
+            while True:
+                req = self._take(large, slot)
+                if req is None:
+                    return
+                try:
+                    need = self._bytes(req.n)
+                except Exception as e:  # noqa: BLE001 - recorded on the request
+                    req.error = f"{type(e).__name__}: {e}"
+                    self._finish(req, None, float("nan"), None, name)
+                    continue
+                if need + self.FIXED > self.budget.total:
+                    req.error = "FramError: workspace exceeds the HBM budget"
+                    self._finish(req, None, float("nan"), None, name)
+                    continue
+                if not self._reserve(slot, need):
+                    return
+                try:
+                    perm, obj, st = ctx.solve(req.A, req.B, theta=self.theta, iters=self.iters,
+                                              tol=self.tol, sdsn_mode="stream", **self.opts)
+                except Exception as e:  # noqa: BLE001 - recorded on the request
+                    req.error = f"{type(e).__name__}: {e}"
+                    perm, obj, st = None, float("nan"), None
+                self._finish(req, perm, obj, st, name)
+        finally:
+            if slot["held"]:
+                self.budget.release(slot["held"])
 
     # ------------------------------------------------------------- trace replay
     def replay(self, requests: list[Request], timeout_s: float = 600.0) -> list[Request]:
@@ -183,14 +266,24 @@ class Server:
         self.shutdown()
         return list(self.completed)
 
+    def resident_bytes(self) -> int:
+        """Device memory all slot contexts hold (fram_resident_bytes)."""
+        return sum(int(getattr(c, "resident_bytes", lambda: 0)()) for _, c, _ in self.slots)
 
-def summarize(done: list[Request], warmup_s: float, duration_s: float) -> dict:
-    """p50 / p99 latency and throughput over requests arriving after warm-up."""
-    meas = [r for r in done if r.arrival >= warmup_s and r.done >= 0]
+
+def summarize(done: list[Request], warmup_s: float, duration_s: float,
+              offered: int | None = None) -> dict:
+    """p50 / p99 latency and throughput over the requests arriving after
+    warm-up that completed without error; failed requests are counted apart,
+    and `offered` (requests submitted after warm-up) shows any left unfinished."""
+    after = [r for r in done if r.arrival >= warmup_s and r.done >= 0]
+    meas = [r for r in after if not r.error]
     lat = np.array([r.latency_ms for r in meas]) if meas else np.array([np.nan])
     last = max((r.done for r in meas), default=warmup_s)
     return dict(
         requests=len(meas),
+        failed=len(after) - len(meas),
+        unfinished=(offered - len(after)) if offered is not None else 0,
         p50_ms=float(np.percentile(lat, 50)),
         p99_ms=float(np.percentile(lat, 99)),
         mean_ms=float(np.mean(lat)),

@@ -214,3 +214,33 @@ def test_sizes_above_the_maximum_are_rejected_before_device_use(hctx):
     assert hctx.lib.fram_workspace_bytes(n, 0, 0) == 0
     W = np.zeros(1, dtype=np.float32)
     assert hctx.lib.fram_assign(hctx.handle, W.ctypes.data, n, perm.ctypes.data) == F.FRAM_EINVAL
+
+
+def test_warm_start_arguments_are_validated_before_device_use(hctx):
+    # A non-finite host warm start is rejected on the host; fram_solve_many
+    # takes no warm start or final iterate (Algorithm 1 step 1 per pair).
+    A, B = _graph(), _graph(seed=1)
+    N0 = np.full((6, 6), 1.0 / 6, dtype=np.float32)
+    N0[2, 3] = np.nan
+    o = F.fram_default_options()
+    o.N0 = N0.ctypes.data
+    assert _raw_solve(hctx, A, B, 6, opts=o) == F.FRAM_EINVAL
+    N0[2, 3] = np.inf
+    assert _raw_solve(hctx, A, B, 6, opts=o) == F.FRAM_EINVAL
+    out = np.zeros((6, 6), dtype=np.float32)
+    o2 = F.fram_default_options()
+    o2.N_out = out.ctypes.data
+    perms = [np.zeros(6, dtype=np.int32)]
+    pa = (ctypes.c_void_p * 1)(A.ctypes.data)
+    pb = (ctypes.c_void_p * 1)(B.ctypes.data)
+    pp = (ctypes.c_void_p * 1)(perms[0].ctypes.data)
+    ns = np.array([6], dtype=np.int32)
+    objs = np.zeros(1)
+    st = F.load_library().fram_solve_many_ex(hctx.handle, 1, pa, pb, ns.ctypes.data, 2.0, 5, 0.0,
+                                             ctypes.byref(o2), pp, objs.ctypes.data, None)
+    assert st == F.FRAM_EINVAL
+
+
+def test_default_options_have_no_warm_start():
+    o = F.fram_default_options()
+    assert not o.N0 and not o.N_out

@@ -66,10 +66,11 @@ def test_sdsn_matches_oracle(ctx, n, theta):
     k = st["sdsn_passes"]
     _, info = O.sdsn(K.astype(np.float64), theta, gth, 20000)
     # Near gamma_tol gamma falls by ~1% per pass at theta = 10, and FP32
-    # rounding of the pass output slows that tail: an FP32 model of the same
-    # arithmetic in numpy needs the same ~10% more passes than FP64 (e.g. 1448
-    # vs 1308 at n = 1000), so the pass count is compared loosely and the
-    # matrices are compared exactly after the GPU's own pass count.
+    # rounding of the pass output slows that tail: an FP32 model of the pass
+    # needs up to ~11% more passes than FP64 on these inputs (1448 vs 1308 at
+    # n = 1000; pinned on the CPU by tests/test_sdsn_fp32_rounding.py), so the
+    # pass count is compared with that slack and the matrices are compared
+    # element-wise after the GPU's own pass count.
     slack = 0.05 if theta <= 2.0 else 0.15
     assert abs(k - info.passes) <= max(3, int(slack * info.passes)), (k, info.passes)
     D, _ = O.sdsn(K.astype(np.float64), theta, 0.0, max_passes=k)
@@ -133,3 +134,24 @@ def test_modes_match_oracle_theta10(ctx, mode):
     k = st["sdsn_passes"]
     D, _ = O.sdsn(K.astype(np.float64), 10.0, 0.0, max_passes=k)
     assert np.abs(X - D).max() <= k * 2e-6 / n + 1e-7
+
+
+@pytest.mark.parametrize("n,tile", [(4000, 256), (4097, 256), (4097, 128)])
+def test_sdsn_matches_oracle_at_full_size(ctx, n, tile):
+    # The bench's layout (tile 256: a 16 x 16 grid at n = 4000) and ragged
+    # grids past 16 tiles per side (n = 4097: 17 x 17 of 256, 33 x 33 of 128),
+    # whose row/column partial chains take the general summation path.  A
+    # fixed pass count on both sides (the FP64 oracle takes ~0.3 s per pass
+    # at this size), then element-wise with the same error budget as above.
+    rng = np.random.default_rng(n + tile)
+    K = (rng.random((n, n)) ** 2).astype(np.float32)
+    k = 24
+    X, st = ctx.sdsn_project(K, 2.0, gamma_tol=1e-6, sdsn_max=k, tile=tile, sdsn_mode="stream")
+    assert st["sdsn_passes"] == k and st["gemm_tile"] == tile
+    D, info = O.sdsn(K.astype(np.float64), 2.0, 0.0, max_passes=k)
+    assert info.passes == k
+    err = np.abs(X.astype(np.float64) - D).max()
+    assert err <= k * 2e-6 / n + 1e-7, err
+    # gamma of the output, as the oracle defines it (Sec. 5.2), in FP64
+    g_or = D.sum() / n - 1.0
+    assert abs(st["gamma"] - g_or) <= 1e-4

@@ -111,8 +111,96 @@ def test_admission_respects_budget():
             for i in range(4)]
     FakeContext.peak = 0
     srv = Server(hbm_budget_bytes=1, large_workers=3, small_n=256, context_factory=FakeContext)
+    one = srv._bytes(600) + Server.FIXED
+    srv.budget.total = srv.budget.free = one + one // 2
     done = srv.replay(reqs, timeout_s=60)
-    assert len(done) == 4 and FakeContext.peak == 1
+    assert len(done) == 4 and FakeContext.peak == 1 and not any(r.error for r in done)
+
+
+def test_request_larger_than_the_budget_is_refused_not_run():
+    reqs = [Request(rid=0, A=np.ones((600, 600)), B=np.ones((600, 600)), arrival=0.0)]
+    srv = Server(hbm_budget_bytes=1 << 20, large_workers=1, small_workers=0, small_n=256,
+                 context_factory=FakeContext)
+    done = srv.replay(reqs, timeout_s=30)
+    assert len(done) == 1 and "HBM budget" in done[0].error and done[0].perm is None
+
+
+class FailingContext(FakeContext):
+    """Raises for every request whose A[0, 1] is negative (a stand-in for a
+    FramError from the library), solves the others."""
+
+    def solve(self, A, B, **kw):
+        if A[0, 1] < 0:
+            raise RuntimeError("fram_solve_ex: status 4 (numeric)")
+        return super().solve(A, B, **kw)
+
+
+def test_a_failing_request_is_reported_and_its_slot_keeps_serving():
+    reqs = _trace(30, 500.0, 3, n_hi=200)
+    for r in reqs[::7]:
+        r.A = r.A.copy()
+        r.A[0, 1] = -1.0
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=1, small_workers=1, small_n=256,
+                 context_factory=FailingContext)
+    done = srv.replay(reqs, timeout_s=60)
+    assert len(done) == len(reqs)
+    bad = {r.rid for r in done if r.error}
+    assert bad == {r.rid for r in reqs[::7]}
+    assert all(r.perm is not None for r in done if not r.error)
+    s = summarize(done, warmup_s=0.0, duration_s=reqs[-1].arrival, offered=len(reqs))
+    assert s["failed"] == len(bad) and s["requests"] == len(reqs) - len(bad)
+    assert s["unfinished"] == 0
+
+
+class ResidentContext(FakeContext):
+    """Holds a workspace like a libfram context: it grows to the largest
+    request's bytes and is released only by trim(); the sum over all live
+    contexts is checked against the budget on every change."""
+    held = {}
+    peak_total = 0
+
+    def __init__(self, device=0):
+        super().__init__(device)
+        self.ws = 0
+        self.fixed = 0
+
+    def _account(self):
+        with FakeContext.lock:
+            ResidentContext.held[id(self)] = self.ws + self.fixed
+            ResidentContext.peak_total = max(ResidentContext.peak_total,
+                                             sum(ResidentContext.held.values()))
+
+    def solve(self, A, B, **kw):
+        from paper_2508_00887_amd.serve import Server as S
+        need = S._bytes(self.server, A.shape[0])
+        self.fixed = 8192
+        self.ws = max(self.ws, need)
+        self._account()
+        return super().solve(A, B, **kw)
+
+    def trim(self):
+        self.ws = 0
+        self._account()
+
+    def resident_bytes(self):
+        return self.ws + self.fixed
+
+
+def test_memory_held_by_all_slots_stays_within_the_budget():
+    reqs = _trace(80, 300.0, 5, n_lo=30, n_hi=1200)
+    ResidentContext.held = {}
+    ResidentContext.peak_total = 0
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=3, small_workers=3, small_n=256,
+                 context_factory=ResidentContext)
+    for _, c, _ in srv.slots:
+        c.server = srv
+    largest = max(srv._bytes(r.n) for r in reqs) + Server.FIXED
+    budget = int(1.6 * largest)
+    srv.budget.total = srv.budget.free = budget
+    done = srv.replay(reqs, timeout_s=120)
+    assert len(done) == len(reqs) and not any(r.error for r in done)
+    assert 0 < ResidentContext.peak_total <= budget
+    assert srv.budget.free == budget  # every charge returned at shutdown
 
 
 @pytest.mark.gpu
