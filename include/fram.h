@@ -100,6 +100,10 @@ typedef struct {
                             the loop                                                   */
   double ms_discretize;  /* (profile 1 or 2) Algorithm 1 step 10 on the device: row
                             argmax, column minima and the exact assignment           */
+  int sdsn_onchip;       /* projections run by the on-chip SDSN launch                 */
+  int sdsn_fallbacks;    /* on-chip launches whose workgroups could not all be resident
+                            at once (compute units held by other work past a 10 ms
+                            bound): nothing was done and the projection streamed     */
 } fram_stats;
 
 typedef struct {
@@ -114,11 +118,18 @@ typedef struct {
                             permutation for w consecutive iterations (a second stop
                             rule beside delta <= tol, for precisions whose delta
                             levels off above tol); 0 = off (default)                 */
-  int sdsn_mode;         /* 0 = automatic (currently the streaming passes), 1 = one
-                            streaming launch per SDSN pass, 2 = on-chip: all passes of
-                            a projection in one cooperative launch with the iterate
-                            held in registers (FRAM_EINVAL if the device cannot hold
-                            it; fram_sdsn_project only)                               */
+  int sdsn_mode;         /* 0 = automatic: on-chip whenever the grid fits the device
+                            (n up to ~4400) and the matrix is more than one tile, else
+                            streaming; 1 = one streaming launch per SDSN pass; 2 =
+                            on-chip: all passes of a projection (and, in solves, the N
+                            update of Algorithm 1 step 7) in one launch with the
+                            iterate held in registers (FRAM_EINVAL if the device cannot
+                            hold it).  On-chip launches are ordered one after another
+                            across all contexts and streams of the process; one whose
+                            workgroups cannot all be resident within 10 ms (compute
+                            units held by other work) does nothing and that projection
+                            streams instead (fram_stats.sdsn_fallbacks).  Both modes
+                            give the same iterates bit for bit.                        */
   int stall_iters;       /* w > 0: also stop once delta has stalled at the precision's
                             floor: after delta <= stall_delta, w consecutive iterations
                             without a new smallest delta; 0 = off (default)            */

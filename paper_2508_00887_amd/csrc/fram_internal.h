@@ -14,7 +14,8 @@ namespace fram {
 struct DevState {
   int done;          // SDSN converged (or capped) for the current projection
   int passes;        // SDSN passes made by the current projection
-  int invalid;       // flags: 1 non-finite, 2 negative, 4 asymmetric input; 8 barrier timeout
+  int invalid;       // flags: 1 non-finite, 2 negative, 4 asymmetric input; 8 barrier
+                     // timeout, 16 on-chip roll call failed (on-chip SDSN)
   int total_passes;  // passes summed over projections (on-chip SDSN path)
   int max_passes;    // largest pass count of one projection (on-chip SDSN path)
   int capped;        // some projection hit the pass cap (on-chip SDSN path)
@@ -79,8 +80,16 @@ hipError_t launch_sdsn_pass(int bm, float* X, int n, int np, Partials in, Partia
                             DevState* st, int k, int max_passes, double theta,
                             double gamma_tol, hipStream_t s, double fixed_scale = 0.0);
 
-// Arguments of the on-chip SDSN projection (sdsn_persistent.hip).
-struct PersistArgs {
+// Bits of DevState::invalid set by the on-chip SDSN.
+constexpr int kInvalidBarrier = 8;    // a grid barrier timed out (launch aborted)
+constexpr int kInvalidRollCall = 16;  // not all workgroups became resident: nothing done
+// Largest on-chip grid (workgroups) the synchronisation counters allow.
+constexpr long kOnchipMaxGrid = 4096;
+// Bytes of the synchronisation block of one on-chip launch (zeroed before it).
+constexpr size_t kOnchipSyncBytes = 2048;
+
+// Arguments of the on-chip SDSN projection (sdsn_onchip.hip).
+struct OnchipArgs {
   const float* src;  // input matrix, leading dimension ld_src
   int ld_src;
   int src_vec;       // 1: rows of src are 16-byte aligned (float4 loads)
@@ -88,10 +97,10 @@ struct PersistArgs {
   int n, np;
   Partials p[2];     // ping-pong partial sets (set 0 also gets tile maxima)
   DevState* st;
-  unsigned long long* flags;      // grid barrier: gridDim.x + 1 epoch flags
-  unsigned long long epoch_base;  // larger than every epoch of earlier launches
+  unsigned* sync;    // kOnchipSyncBytes, zero at launch: barrier counters, abort flag
+  long long roll_ticks;  // bound (wall-clock ticks) on the roll call
+  long long wait_ticks;  // bound on every later barrier wait
   int max_passes;
-  int spin_limit;    // bound on each barrier wait (sleep iterations)
   double theta, gamma_tol;
   float* N;          // optional fused update: N <- (1-alpha) N + alpha D
   void* Nlp;         // GEMM-type copy of N (nlp_kind 1 = bf16, 2 = f16, 0 = none)
@@ -100,12 +109,14 @@ struct PersistArgs {
   double* dpart;     // FP64 delta partials, 2 per workgroup (tile order)
 };
 
-// True if one cooperative launch of nb*nb workgroups of the BM variant fits
-// on `device` (all workgroups co-resident).
-bool sdsn_persistent_fits(int device, int bm, int np);
+// True if the nb*nb workgroups of the BM variant can all be resident on
+// `device` at once (an idle device; the roll call covers the rest).
+bool sdsn_onchip_fits(int device, int bm, int np);
 
-// Every SDSN pass of one projection in one cooperative launch (grid nb*nb).
-hipError_t launch_sdsn_persistent(int bm, const PersistArgs& a, hipStream_t s);
+// Every SDSN pass of one projection in one launch (grid nb*nb).  The caller
+// zeroes a.sync on the same stream first and orders these launches across
+// streams (see runtime.hip).
+hipError_t launch_sdsn_onchip(int bm, const OnchipArgs& a, hipStream_t s);
 
 // st->delta from `nblocks` pairs of FP64 partial sums (num, den).
 hipError_t launch_delta_final(const double* part, int nblocks, DevState* st, hipStream_t s);

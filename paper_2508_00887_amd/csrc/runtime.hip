@@ -41,8 +41,8 @@ struct fram_ctx {
   std::string err;
   fram_stats last{};
   int fit_bm = 0, fit_np = 0, fit_ok = 0;  // cached on-chip SDSN feasibility
-  unsigned long long launches = 0;         // on-chip launches (barrier epochs)
-  unsigned long long* flags = nullptr;     // grid-barrier flags, zeroed once, own allocation
+  unsigned* sync = nullptr;                // on-chip SDSN barrier block (own allocation)
+  long long clock_khz = 0;                 // device wall-clock rate (on-chip wait bounds)
   // Asynchronous launch timing (profile = 2): event pairs recorded around
   // launches and read once the stream has passed them.
   struct Timing {
@@ -63,7 +63,6 @@ struct fram_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kFlagBytes = 8 * 1024;  // >= 8 * (max on-chip grid + 1)
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Tile table set by fram_set_tile_table (an autotuner's choice per size
@@ -157,13 +156,10 @@ Layout plan(int n, Elem e, int tile, Use use, bool node = false, bool dspfp = fa
 
 bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP16; }
 
-// Paths of the solver that are switched off: a device fault seen in solve
-// runs that used them has not been traced to its cause yet, so the solver
-// keeps to the kernels whose runs have been clean (streaming SDSN passes,
-// single-pair path).  With these set, sdsn_mode "onchip" is rejected by the
-// solvers and fram_solve_many solves pair by pair.  The on-chip projection of
-// fram_sdsn_project is not affected.
-constexpr bool kSolveOnchip = false;
+// Devices whose on-chip SDSN launches are ordered (see OnchipGate).
+constexpr int kMaxGateDevices = 64;
+// The batched kernel stays off until its own runs on the device are clean;
+// fram_solve_many then solves pair by pair.
 constexpr bool kBatchedKernel = false;
 // Most worker contexts of one fram_solve_many call (fram_options.many_workers).
 constexpr int kMaxManyWorkers = 32;
@@ -228,11 +224,11 @@ fram_status ensure_device(fram_ctx* c) {
   HIPCHK(hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault));
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
-  // Barrier flags of the on-chip SDSN launches: a fixed allocation, zeroed
-  // once; epochs only grow, so stale flags are always below the next epoch.
-  HIPCHK(hipMalloc((void**)&c->flags, kFlagBytes));
-  HIPCHK(fram::launch_zero(c->flags, kFlagBytes, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  // Barrier counters of the on-chip SDSN launches (zeroed before each launch).
+  HIPCHK(hipMalloc((void**)&c->sync, fram::kOnchipSyncBytes));
+  int khz = 0;
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+  c->clock_khz = khz > 0 ? khz : 100000;
   c->inited = true;
   return FRAM_OK;
 }
@@ -421,49 +417,59 @@ fram_status run_sdsn_passes(fram_ctx* c, const Layout& L, int n, float* X, DevSt
 }
 
 // Decide whether the on-chip SDSN path is used for this layout.
+// Automatic mode takes the on-chip launch whenever the grid fits the device
+// (and a single-tile matrix, whose streaming projection is already one
+// workgroup launch, streams); "stream" never does; "onchip" insists.
 fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool* on) {
   *on = false;
-  // Automatic mode streams: the on-chip launch is taken only when asked for.
-  if (o.sdsn_mode != 2) return FRAM_OK;
-  if (o.sdsn_max > (1 << 24) - 8) {  // barrier epochs of one launch must stay below 2^24
-    if (o.sdsn_mode == 2) {
-      c->err = "sdsn_max too large for the on-chip SDSN path";
-      return FRAM_EINVAL;
-    }
-    return FRAM_OK;
-  }
-  if ((size_t)L.nb * L.nb + 1 > kFlagBytes / sizeof(unsigned long long)) {
-    if (o.sdsn_mode == 2) {
-      c->err = "too many tiles for the on-chip SDSN path";
-      return FRAM_EINVAL;
-    }
-    return FRAM_OK;
+  if (o.sdsn_mode == 1) return FRAM_OK;
+  const bool insist = o.sdsn_mode == 2;
+  if (!insist && L.nb == 1) return FRAM_OK;
+  // Barrier counters reach (passes + 2) * ceil(grid / 8) < 2^32.
+  if (o.sdsn_max > (1 << 22) || c->device >= kMaxGateDevices) {
+    if (!insist) return FRAM_OK;
+    c->err = "sdsn_max too large or device index too high for the on-chip SDSN path";
+    return FRAM_EINVAL;
   }
   if (c->fit_bm != L.bm || c->fit_np != L.np) {
     c->fit_bm = L.bm;
     c->fit_np = L.np;
-    c->fit_ok = fram::sdsn_persistent_fits(c->device, L.bm, L.np) ? 1 : 0;
+    c->fit_ok = fram::sdsn_onchip_fits(c->device, L.bm, L.np) ? 1 : 0;
   }
-  if (!c->fit_ok && o.sdsn_mode == 2) {
+  if (!c->fit_ok) {
+    if (!insist) return FRAM_OK;
     c->err = "on-chip SDSN does not fit this device";
     return FRAM_EINVAL;
   }
-  *on = c->fit_ok != 0;
+  *on = true;
   return FRAM_OK;
 }
 
-// Bound on one grid-barrier wait of the on-chip SDSN, in polls (each a
-// relaxed load of a flag plus a short sleep, about a microsecond): about a
-// second, far above a pass's few microseconds, so a launch whose workgroups
-// cannot all meet (they are not co-resident) ends quickly with an error.
-constexpr int kSpinLimit = 1 << 20;
+// Bounds on the waits of the on-chip SDSN.  The roll call (all workgroups
+// resident) normally completes within microseconds; when kernels of other
+// streams hold compute units longer than this, the launch is abandoned and
+// the projection streams instead.  A pass barrier takes a few microseconds,
+// so its bound only ends a launch that can no longer complete.
+constexpr long long kRollCallMs = 10;
+constexpr long long kBarrierMs = 200;
 
-// One on-chip projection: D = SDSN(src) with every pass in one cooperative
-// launch; optionally writes D to dst (ld np) and/or applies the N update.
+// On-chip SDSN launches are ordered one after the other across all streams of
+// the process on a device: each waits (on the device) for the completion
+// event of the previous one, so no two of these grids, whose workgroups wait
+// for each other, ever compete for compute units.
+struct OnchipGate {
+  std::mutex mu;
+  hipEvent_t last = nullptr;
+};
+OnchipGate g_gate[kMaxGateDevices];
+
+// One on-chip projection: D = SDSN(src) with every pass in one launch;
+// optionally writes D to dst (ld np) and/or applies the N update.  Whether it
+// ran (or the roll call failed and nothing was done) is in st->invalid.
 fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* src, int ld_src,
                             float* dst, float* N, void* Nlp, Elem e, double alpha,
                             DevState* st, double theta, const fram_options& o, hipStream_t s) {
-  fram::PersistArgs a{};
+  fram::OnchipArgs a{};
   a.src = src;
   a.ld_src = ld_src;
   a.src_vec = (ld_src % 4 == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0) ? 1 : 0;
@@ -473,10 +479,10 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   a.p[0] = partials(c, L, 0);
   a.p[1] = partials(c, L, 1);
   a.st = st;
-  a.flags = c->flags;
-  a.epoch_base = (++c->launches) << 24;
+  a.sync = c->sync;
+  a.roll_ticks = c->clock_khz * kRollCallMs;
+  a.wait_ticks = c->clock_khz * kBarrierMs;
   a.max_passes = o.sdsn_max;
-  a.spin_limit = kSpinLimit;
   a.theta = theta;
   a.gamma_tol = o.gamma_tol;
   a.N = N;
@@ -484,7 +490,16 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   a.nlp_kind = (N == nullptr || e == Elem::F32) ? 0 : (e == Elem::BF16 ? 1 : 2);
   a.alpha = (float)alpha;
   a.dpart = at<double>(c, L.upd);
-  HIPCHK(fram::launch_sdsn_persistent(L.bm, a, s));
+  OnchipGate& g = g_gate[c->device];
+  std::lock_guard<std::mutex> lk(g.mu);
+  if (g.last == nullptr) {
+    HIPCHK(hipEventCreateWithFlags(&g.last, hipEventDisableTiming));
+  } else {
+    HIPCHK(hipStreamWaitEvent(s, g.last, 0));
+  }
+  HIPCHK(fram::launch_zero(c->sync, fram::kOnchipSyncBytes, s));
+  HIPCHK(fram::launch_sdsn_onchip(L.bm, a, s));
+  HIPCHK(hipEventRecord(g.last, s));
   return FRAM_OK;
 }
 
@@ -626,6 +641,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   }
 
   int total_passes = 0, last_passes = 0, max_passes_seen = 0, it = 0;
+  int total_passes_streamed = 0;
   bool any_capped = false, converged = false;
   double gamma = 0.0, delta = 0.0;
   int est = 8;
@@ -635,17 +651,11 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   bool stalled = false;
   double dmin = 0.0;  // smallest delta since delta first fell to stall_delta (0: not yet)
   Prof prof{o.profile, c, s, 0.0f};
-  // The on-chip SDSN inside the outer loop is switched off (see kSolveOnchip);
-  // every solve projects with the streaming passes.
   bool onchip = false;
-  if (kSolveOnchip) {
+  if (!dspfp) {
     fram_status q = use_onchip(c, L, o, &onchip);
     if (q != FRAM_OK) return q;
-  } else if (o.sdsn_mode == 2) {
-    c->err = "the on-chip SDSN is disabled inside solves (use sdsn_mode stream or auto)";
-    return FRAM_EINVAL;
   }
-  if (dspfp) onchip = false;
   for (it = 1; it <= iters; ++it) {
     // Step 5: X = A N B as W = B N^T, X = A W^T.
     fram_status r = timed(prof, &stt->ms_gemm, &stt->gemm_launches, [&] {
@@ -656,8 +666,12 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       return fram::launch_gemm_nt(e, L.bm, Alp, W, X, true, n, L.np, L.np, s, Kp);
     });
     if (r != FRAM_OK) return r;
+    bool streamed = !onchip;
+    bool state_fresh = false;  // c->hst holds the state after this iteration's update
     if (onchip) {
-      // Steps 6-8 in one cooperative launch (+ the delta reduction).
+      // Steps 6-8 in one launch (+ the delta reduction), then the state: the
+      // launch either ran every pass or, when its roll call failed, did
+      // nothing, and this iteration's projection streams instead.
       r = timed(prof, &stt->ms_sdsn, nullptr, [&] {
         fram_status q = run_sdsn_onchip(c, L, n, X, L.np, nullptr, N, Nlp, e, o.alpha, st,
                                         theta, o, s);
@@ -668,7 +682,32 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
         return fram::launch_delta_final(at<double>(c, L.upd), L.nb * L.nb, st, s);
       });
       if (r != FRAM_OK) return r;
-    } else {
+      r = read_state(c, st, s);
+      if (r != FRAM_OK) return r;
+      if (c->hst->invalid & fram::kInvalidBarrier) {
+        c->err = "on-chip SDSN barrier timed out";
+        return FRAM_EDEVICE;
+      }
+      if (c->hst->invalid & fram::kInvalidRollCall) {
+        HIPCHK(fram::launch_zero(&st->invalid, sizeof(int), s));
+        stt->sdsn_fallbacks += 1;
+        streamed = true;
+      } else {
+        const int passes = c->hst->passes;
+        gamma = c->hst->gamma;
+        if (!std::isfinite(gamma)) {
+          c->err = "non-finite gamma in SDSN";
+          return FRAM_ENUMERIC;
+        }
+        total_passes += passes;
+        last_passes = passes;
+        max_passes_seen = std::max(max_passes_seen, passes);
+        any_capped = any_capped || (passes >= o.sdsn_max && !(gamma <= o.gamma_tol));
+        stt->sdsn_onchip += 1;
+        state_fresh = true;
+      }
+    }
+    if (streamed) {
       r = timed(prof, &stt->ms_stats, nullptr, [&] {
         return fram::launch_tile_stats(L.bm, X, L.np, nullptr, n, L.np, partials(c, L, 0), st,
                                        s);
@@ -682,6 +721,7 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       if (r != FRAM_OK) return r;
       est = passes;
       total_passes += passes;
+      total_passes_streamed += passes;
       last_passes = passes;
       max_passes_seen = std::max(max_passes_seen, passes);
       any_capped = any_capped || capped;
@@ -706,11 +746,9 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
     }
     const bool watch_stall = o.stall_iters > 0;
     if (tol > 0.0 || track || watch_stall || it == iters) {
-      r = read_state(c, st, s);
-      if (r != FRAM_OK) return r;
-      if (c->hst->invalid & 8) {
-        c->err = "on-chip SDSN barrier timed out";
-        return FRAM_EDEVICE;
+      if (!state_fresh || track) {
+        r = read_state(c, st, s);
+        if (r != FRAM_OK) return r;
       }
       delta = c->hst->delta;
       // DSPFP's criterion is +inf while the previous iterate is 0.
@@ -758,24 +796,8 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
   if (r != FRAM_OK) return r;
   r = flush_timings(c);
   if (r != FRAM_OK) return r;
-  if (onchip) {
-    // finish_discretise left the device state in c->hst.
-    if (c->hst->invalid & 8) {
-      c->err = "on-chip SDSN barrier timed out";
-      return FRAM_EDEVICE;
-    }
-    total_passes = c->hst->total_passes;
-    max_passes_seen = c->hst->max_passes;
-    last_passes = c->hst->passes;
-    any_capped = c->hst->capped != 0;
-    gamma = c->hst->gamma;
-    if (!std::isfinite(gamma)) {
-      c->err = "non-finite gamma in SDSN";
-      return FRAM_ENUMERIC;
-    }
-  }
-  if (o.profile != 0 && onchip) stt->sdsn_launches = it;  // one launch per projection
-  if (o.profile == 2 && !onchip) stt->sdsn_launches = total_passes;
+  if (o.profile == 1) stt->sdsn_launches += stt->sdsn_onchip;  // streamed passes counted
+  if (o.profile == 2) stt->sdsn_launches = total_passes_streamed + stt->sdsn_onchip;
   stt->outer_iters = it;
   stt->sdsn_passes = total_passes;
   stt->sdsn_passes_last = last_passes;
@@ -926,7 +948,7 @@ void fram_destroy(fram_ctx* c) {
     if (c->hst) (void)hipHostFree(c->hst);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->flags) (void)hipFree(c->flags);
+    if (c->sync) (void)hipFree(c->sync);
     if (c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -934,7 +956,7 @@ void fram_destroy(fram_ctx* c) {
 
 size_t fram_resident_bytes(const fram_ctx* c) {
   if (!c) return 0;
-  size_t b = c->ws_bytes + (c->flags ? kFlagBytes : 0);
+  size_t b = c->ws_bytes + (c->sync ? fram::kOnchipSyncBytes : 0);
   for (const fram_ctx* w : c->workers) b += fram_resident_bytes(w);
   return b;
 }
@@ -1104,6 +1126,7 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   bool onchip = false;
   r = use_onchip(c, L, o, &onchip);
   if (r != FRAM_OK) return r;
+  bool streamed = !onchip;
   if (onchip) {
     Prof prof{o.profile, c, s, 0.0f};
     r = timed(prof, &stt.ms_sdsn, nullptr, [&] {
@@ -1114,19 +1137,28 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
     if (r != FRAM_OK) return r;
     r = read_state(c, st, s);
     if (r != FRAM_OK) return r;
-    if (c->hst->invalid & 8) {
+    if (c->hst->invalid & fram::kInvalidBarrier) {
       c->err = "on-chip SDSN barrier timed out";
       return FRAM_EDEVICE;
     }
-    passes = c->hst->passes;
-    gamma = c->hst->gamma;
-    capped = c->hst->capped != 0;
-    stt.sdsn_launches = passes;
-    if (!std::isfinite(gamma)) {
-      c->err = "non-finite gamma in SDSN";
-      return FRAM_ENUMERIC;
+    if (c->hst->invalid & fram::kInvalidRollCall) {
+      // Nothing was done (the input is untouched): stream instead.
+      HIPCHK(fram::launch_zero(&st->invalid, sizeof(int), s));
+      stt.sdsn_fallbacks = 1;
+      streamed = true;
+    } else {
+      passes = c->hst->passes;
+      gamma = c->hst->gamma;
+      capped = passes >= o.sdsn_max && !(gamma <= o.gamma_tol);
+      stt.sdsn_launches = 1;
+      stt.sdsn_onchip = 1;
+      if (!std::isfinite(gamma)) {
+        c->err = "non-finite gamma in SDSN";
+        return FRAM_ENUMERIC;
+      }
     }
-  } else {
+  }
+  if (streamed) {
     HIPCHK(fram::launch_tile_stats(L.bm, dK, ldk, X, n, L.np, partials(c, L, 0), st, s));
     r = run_sdsn_passes(c, L, n, X, st, lambda, o, 8, s, &passes, &gamma, &capped, &stt);
     if (r != FRAM_OK) return r;
@@ -1135,7 +1167,7 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
   HIPCHK(hipStreamSynchronize(s));
   r = flush_timings(c);
   if (r != FRAM_OK) return r;
-  if (o.profile == 2) stt.sdsn_launches = onchip ? 1 : passes;
+  if (o.profile == 2) stt.sdsn_launches = streamed ? passes : 1;
   stt.sdsn_passes = passes;
   stt.sdsn_passes_last = passes;
   stt.sdsn_passes_max = passes;

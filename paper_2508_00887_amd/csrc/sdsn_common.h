@@ -163,14 +163,22 @@ __device__ __forceinline__ void tile_step_sums(const float4& y, int rl, double* 
   cacc.w += y.w;
 }
 
+// Plain stores (the streaming kernels: other workgroups read the values in a
+// later launch).
+struct PlainStore {
+  template <typename T>
+  __device__ __forceinline__ void operator()(T* p, T v) const { *p = v; }
+};
+
 // Writes the FP64 row partials, column partials and tile total of one tile
 // from s_rowsum and the per-lane column sums cacc: rowp[bn * np + row],
 // colp[bm * np + col], tot[bm * nb + bn].  s_colred holds 16 x BM floats.
-template <int BM>
+// `st` performs the global stores.
+template <int BM, typename Store = PlainStore>
 __device__ __forceinline__ void tile_partials(const float4& cacc, const double* s_rowsum,
                                               float (*s_colred)[BM], double* s_red,
                                               double* rowp, double* colp, double* tot, int bm,
-                                              int bn, int nb, int np) {
+                                              int bn, int nb, int np, Store st = Store()) {
   using TS = TileShape<BM>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -182,7 +190,7 @@ __device__ __forceinline__ void tile_partials(const float4& cacc, const double* 
   double rowsum = 0.0;
   if (tid < BM) {
     rowsum = s_rowsum[tid];
-    at_u32(rowp, (unsigned)(bn * np + bm * BM + tid)) = rowsum;
+    st(&at_u32(rowp, (unsigned)(bn * np + bm * BM + tid)), rowsum);
   }
   {  // column partials: 4 threads per column, fixed order, FP64
     const int c = tid >> 2, p = tid & 3;
@@ -191,10 +199,10 @@ __device__ __forceinline__ void tile_partials(const float4& cacc, const double* 
     for (int u = 0; u < 4; ++u) v += (double)s_colred[p * 4 + u][c];
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
-    if (p == 0) at_u32(colp, (unsigned)(bm * np + bn * BM + c)) = v;
+    if (p == 0) st(&at_u32(colp, (unsigned)(bm * np + bn * BM + c)), v);
   }
   const double tt = block_sum<TS::NT>(rowsum, s_red);
-  if (tid == 0) tot[bm * nb + bn] = tt;
+  if (tid == 0) st(&tot[bm * nb + bn], tt);
 }
 
 }  // namespace

@@ -1,0 +1,396 @@
+// SDSN (Algorithm 2) with the iterate resident on chip.
+//
+// The streaming pass in sdsn.hip reads and writes all of X once per SDSN
+// iteration, so its time is bounded by HBM.  Here one launch runs every pass
+// of one projection: each workgroup keeps its BM x BM tile of X in VGPRs for
+// the whole projection (64 floats per lane at BM = 256 with 1024 lanes; the
+// n = 4000 iterate, 64 MB, fits in the 128 MB register file of 256 CUs).  Per
+// pass only the tile's row/column partial sums (FP64) and its total cross the
+// chip: they are written to a ping-pong buffer, the workgroups meet at a
+// grid-wide barrier, and every workgroup then reads the partials of its own
+// rows and columns and all tile totals.  Every workgroup evaluates the same
+// FP64 gamma = 1^T Y 1 / n - 1 (Sec. 5.2) from the same totals in the same
+// order, so all of them leave the pass loop at the same pass.
+//
+// The same launch optionally finishes Algorithm 1 steps 7-8: with D = Y still
+// in registers it updates N <- (1-alpha) N + alpha D, writes the GEMM-type
+// copy of N and FP64 partial sums for delta, so X is never written back.
+//
+// The pass arithmetic and every reduction are those of sdsn.hip (shared in
+// sdsn_common.h), so both kernels give bit-identical iterates:
+// Y = max(0, fma(s, x, alpha_i + beta_j)) with the symmetric FP64 split of the
+// P1 correction (eq. P1_sol).
+//
+// Co-residency.  A workgroup that waits at the barrier holds its compute
+// unit, so the launch makes progress only if all of its workgroups are
+// resident at once.  Three rules make a wait that can never end impossible:
+//  * roll call: every workgroup first checks in and waits, for a bounded time,
+//    until the whole grid has; if it has not, every workgroup leaves before
+//    touching any data (late ones see the abort flag and leave at once), the
+//    state records the fallback, and the caller runs the streaming passes,
+//    which read the untouched input;
+//  * every later wait is bounded too, and a timeout aborts the whole grid;
+//  * the host orders the launches of this kernel one after the other across
+//    every stream of the process (each waits for the previous one's
+//    completion), so two such grids never compete for compute units; other
+//    kernels only delay a roll call, since they never wait for each other.
+//
+// Barrier.  Arrival is counted per group of workgroups (blockIdx mod 8: the
+// XCD the hardware dispatches it to), and the last arrival of a group bumps
+// one release counter that every workgroup polls, so each pass costs a few
+// atomics per group and one poll target instead of all-to-all flags
+// (measured on MI355X with 256 workgroups, barrier plus the partial-sum
+// exchange: 4.9 us per pass, against 9.2 us with one counter for all).  The counters live in a per-context block that
+// the host zeroes before each launch (stream-ordered), and only grow within
+// a launch.
+#include "fram_internal.h"
+#include "sdsn_common.h"
+
+namespace fram {
+namespace {
+
+// Fields of the synchronisation block, each in its own 128-byte line.
+constexpr int kLine = 32;  // unsigned ints per line
+__device__ __forceinline__ unsigned* sync_group(unsigned* sy, int g) { return sy + g * kLine; }
+__device__ __forceinline__ unsigned* sync_release(unsigned* sy) { return sy + 8 * kLine; }
+__device__ __forceinline__ unsigned* sync_abort(unsigned* sy) { return sy + 9 * kLine; }
+__device__ __forceinline__ unsigned* sync_roll(unsigned* sy) { return sy + 10 * kLine; }
+
+__device__ __forceinline__ unsigned ld_agent(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Data that crosses the chip within the launch (partials, totals, maxima) is
+// stored and loaded with agent-scope atomics: the stores write through to the
+// device-coherent level and the loads read from it, so no cache write-back or
+// invalidation is needed around the barrier (measured on MI355X: 4.9 us per
+// pass with 256 workgroups, against 9.7 us with a release/acquire fence pair
+// around plain accesses).
+struct CoherentStore {
+  template <typename T>
+  __device__ __forceinline__ void operator()(T* p, T v) const {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *p >= target, the abort flag is set, or `limit`
+// wall-clock ticks pass (then it sets the abort flag itself).  The result is
+// the same in every thread of the workgroup.
+__device__ bool wait_until(unsigned* p, unsigned target, unsigned* abortf, long long limit,
+                           int* s_ok) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    while (ld_agent(p) < target) {
+      if (ld_agent(abortf) != 0) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Barrier number `epoch` (1, 2, ...).  Every wave waits until its coherent
+// stores have completed (the release half: on this hardware a store counted
+// complete has reached the device-coherent level), then thread 0 bumps the
+// group counter; the group's last arrival bumps the release counter.  The
+// wait ends when all groups are complete (or on abort / timeout); the
+// coherent loads issued after it (the acquire half) see every store made
+// before any arrival.
+__device__ bool grid_barrier(unsigned* sy, unsigned epoch, long long limit, int* s_ok) {
+  const int G = gridDim.x;
+  const int g = blockIdx.x & 7;
+  const int groups = G < 8 ? G : 8;
+  const unsigned gsize = (unsigned)((G - g + 7) / 8);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned old =
+        __hip_atomic_fetch_add(sync_group(sy, g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == epoch * gsize - 1u)
+      __hip_atomic_fetch_add(sync_release(sy), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return wait_until(sync_release(sy), epoch * (unsigned)groups, sync_abort(sy), limit, s_ok);
+}
+
+template <int BM>
+__global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
+  using TS = TileShape<BM>;
+  constexpr int NT = TS::NT;
+  constexpr int LPR = TS::LPR;
+  constexpr int RPW = TS::RPW;
+  constexpr int STEPS = TS::STEPS;
+  __shared__ double s_rowsum[BM];
+  __shared__ float s_colred[16][BM];
+  __shared__ float s_a[BM];
+  __shared__ float s_b[BM];
+  __shared__ double s_red[NT / 64];
+  __shared__ double s_chain[2][4][BM];
+  __shared__ int s_ok;
+
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+
+  // ---- roll call: nothing is read or written before the whole grid is in
+  if (tid == 0)
+    __hip_atomic_fetch_add(sync_roll(a.sync), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!wait_until(sync_roll(a.sync), (unsigned)G, sync_abort(a.sync), a.roll_ticks, &s_ok)) {
+    if (tid == 0) atomicOr(&a.st->invalid, kInvalidRollCall);
+    return;
+  }
+
+  const int lane = tid & 63;
+  // Wave index as a scalar: row bounds then stay in SGPRs.
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = a.n, np = a.np, nb = np / BM;
+  int t = blockIdx.x;  // tile index
+  if ((G & 7) == 0) t = (t & 7) * (G >> 3) + (t >> 3);  // tile rows share an XCD
+  const int bm = t / nb, bn = t % nb;
+  const int q = lane / LPR;
+  const int cl = (lane % LPR) * 4;
+  const int j = bn * BM + cl;
+  const bool c0 = j < n, c1 = j + 1 < n, c2 = j + 2 < n, c3 = j + 3 < n;
+
+  // ---- load the tile (rows >= n and columns >= n read as zero) and emit the
+  // partials and maximum of the input
+  float4 xv[STEPS];
+  float lmax = -INFINITY;
+  float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int stp = 0; stp < STEPS; ++stp) {
+    const int rl = w * 16 + stp * RPW + q;
+    const int i = bm * BM + rl;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n) {
+      const float* row = &at_u32(a.src, (unsigned)(i * a.ld_src + j));
+      // A float4 only where all four columns are inside the matrix: src may
+      // have leading dimension n, so a row's tail must not be read past.
+      if (a.src_vec && c3) {
+        v = *reinterpret_cast<const float4*>(row);
+      } else {
+        v.x = c0 ? row[0] : 0.f;
+        v.y = c1 ? row[1] : 0.f;
+        v.z = c2 ? row[2] : 0.f;
+        v.w = c3 ? row[3] : 0.f;
+      }
+      if (c0) lmax = fmaxf(lmax, v.x);
+      if (c1) lmax = fmaxf(lmax, v.y);
+      if (c2) lmax = fmaxf(lmax, v.z);
+      if (c3) lmax = fmaxf(lmax, v.w);
+    }
+    xv[stp] = v;
+    tile_step_sums<BM>(v, rl, s_rowsum, cacc);
+  }
+  tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.p[0].rowp, a.p[0].colp, a.p[0].tot, bm,
+                    bn, nb, np, CoherentStore());
+  {
+    const float tm = block_max<NT>(lmax, reinterpret_cast<float*>(s_red));
+    if (tid == 0) CoherentStore()(&a.p[0].tmax[bm * nb + bn], tm);
+  }
+
+  unsigned epoch = 1;
+  int k = 1;
+  double gamma = 0.0;
+  bool ok = true;
+  const double dn = (double)n;
+  for (;; ++k, ++epoch) {
+    ok = grid_barrier(a.sync, epoch, a.wait_ticks, &s_ok);
+    if (!ok) break;
+    const Partials in = a.p[(k - 1) & 1];
+    const Partials out = a.p[k & 1];
+    // All reads of the previous pass's partials are issued before they are
+    // combined: the tile totals, then thread (p, r)'s chains p of row r's and
+    // column r's partial sums (combined in a fixed order below).
+    double part = 0.0;
+#pragma unroll 1
+    for (int u = tid; u < nb * nb; u += NT) part += ld_coherent(&at_u32(in.tot, (unsigned)u));
+    float m = -INFINITY;
+    if (k == 1)
+      for (int u = tid; u < nb * nb; u += NT)
+        m = fmaxf(m, ld_coherent(&at_u32(in.tmax, (unsigned)u)));
+    {
+      const int r = tid % BM, p = tid / BM;
+      const unsigned ro = (unsigned)(bm * BM + r), co = (unsigned)(bn * BM + r);
+      auto ldr = [&](int b) { return ld_coherent(&at_u32(in.rowp, (unsigned)(b * np) + ro)); };
+      auto ldc = [&](int b) { return ld_coherent(&at_u32(in.colp, (unsigned)(b * np) + co)); };
+      s_chain[0][p][r] = chain_sum(ldr, nb, p);
+      s_chain[1][p][r] = chain_sum(ldc, nb, p);
+    }
+    const double S = block_sum<NT>(part, s_red);
+    float s = 1.0f;
+    if (k >= 2) {
+      gamma = S / dn - 1.0;
+      if (gamma <= a.gamma_tol || k > a.max_passes) break;
+    } else {
+      m = block_max<NT>(m, reinterpret_cast<float*>(s_red));
+      s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
+    }
+    const double sd = (double)s;
+    const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
+    if (tid < BM) {
+      const double ri = combine4(s_chain[0][0][tid], s_chain[0][1][tid], s_chain[0][2][tid],
+                                 s_chain[0][3][tid]);
+      const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
+                                 s_chain[1][3][tid]);
+      s_a[tid] = (float)(half - sd * ri / dn);
+      s_b[tid] = (float)(half - sd * cj / dn);
+    }
+    __syncthreads();
+    const float4 bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
+    cacc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int stp = 0; stp < STEPS; ++stp) {
+      const int rl = w * 16 + stp * RPW + q;
+      const float ai = s_a[rl];
+      float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (bm * BM + rl < n) {
+        const float4 x = xv[stp];
+        y.x = c0 ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
+        y.y = c1 ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
+        y.z = c2 ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
+        y.w = c3 ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
+      }
+      xv[stp] = y;
+      tile_step_sums<BM>(y, rl, s_rowsum, cacc);
+    }
+    tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, out.rowp, out.colp, out.tot, bm, bn, nb,
+                      np, CoherentStore());
+  }
+  if (!ok) {
+    if (tid == 0) atomicOr(&a.st->invalid, kInvalidBarrier);
+    return;
+  }
+  const int passes = k - 1;
+
+  if (a.dst != nullptr) {
+#pragma unroll
+    for (int stp = 0; stp < STEPS; ++stp) {
+      const int i = bm * BM + w * 16 + stp * RPW + q;
+      if (i < n) *reinterpret_cast<float4*>(&at_u32(a.dst, (unsigned)(i * np + j))) = xv[stp];
+    }
+  }
+  if (a.N != nullptr) {
+    // Algorithm 1 steps 7-8 on this tile: N <- (1-alpha) N + alpha D.
+    const float alpha = a.alpha, c1a = 1.0f - a.alpha;
+    double num = 0.0, den = 0.0;
+    // Fully unrolled (a runtime index into xv would force it out of VGPRs),
+    // in groups of four rows with a scheduling barrier between groups so that
+    // the loads of N do not all become live at once next to the tile.
+#pragma unroll
+    for (int stp = 0; stp < STEPS; ++stp) {
+      if ((stp & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+      const int i = bm * BM + w * 16 + stp * RPW + q;
+      if (i >= n) continue;
+      const unsigned idx = (unsigned)(i * np + j);
+      float4& nref = *reinterpret_cast<float4*>(&at_u32(a.N, idx));
+      const float4 o = nref;
+      const float4 d = xv[stp];
+      float4 nn;
+      nn.x = fmaf(alpha, d.x, c1a * o.x);
+      nn.y = fmaf(alpha, d.y, c1a * o.y);
+      nn.z = fmaf(alpha, d.z, c1a * o.z);
+      nn.w = fmaf(alpha, d.w, c1a * o.w);
+      nref = nn;
+      if (a.nlp_kind == 1) {
+        __bf16* o16 = &at_u32(reinterpret_cast<__bf16*>(a.Nlp), idx);
+        o16[0] = (__bf16)nn.x;
+        o16[1] = (__bf16)nn.y;
+        o16[2] = (__bf16)nn.z;
+        o16[3] = (__bf16)nn.w;
+      } else if (a.nlp_kind == 2) {
+        _Float16* o16 = &at_u32(reinterpret_cast<_Float16*>(a.Nlp), idx);
+        o16[0] = (_Float16)nn.x;
+        o16[1] = (_Float16)nn.y;
+        o16[2] = (_Float16)nn.z;
+        o16[3] = (_Float16)nn.w;
+      }
+      const double ex = (double)nn.x - (double)o.x, ey = (double)nn.y - (double)o.y;
+      const double ez = (double)nn.z - (double)o.z, ew = (double)nn.w - (double)o.w;
+      num += (ex * ex + ey * ey) + (ez * ez + ew * ew);
+      den += ((double)nn.x * nn.x + (double)nn.y * nn.y) +
+             ((double)nn.z * nn.z + (double)nn.w * nn.w);
+    }
+    num = block_sum<NT>(num, s_red);
+    den = block_sum<NT>(den, s_red);
+    if (tid == 0) {
+      a.dpart[2 * (bm * nb + bn)] = num;
+      a.dpart[2 * (bm * nb + bn) + 1] = den;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    DevState* st = a.st;
+    st->done = 1;
+    st->passes = passes;
+    st->gamma = gamma;
+    st->total_passes += passes;
+    if (passes > st->max_passes) st->max_passes = passes;
+    if (passes >= a.max_passes && !(gamma <= a.gamma_tol)) st->capped = 1;
+  }
+}
+
+template <int BM>
+int resident_per_cu() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&sdsn_onchip_kernel<BM>), 4 * BM, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu;
+}
+
+}  // namespace
+
+bool sdsn_onchip_fits(int device, int bm, int np) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return false;
+  const long nb = np / bm;
+  int per_cu = 0;
+  switch (bm) {
+    case 64:
+      per_cu = resident_per_cu<64>();
+      break;
+    case 128:
+      per_cu = resident_per_cu<128>();
+      break;
+    case 256:
+      per_cu = resident_per_cu<256>();
+      break;
+  }
+  return nb * nb <= (long)per_cu * cus && nb * nb <= kOnchipMaxGrid;
+}
+
+hipError_t launch_sdsn_onchip(int bm, const OnchipArgs& a, hipStream_t s) {
+  if (a.np % bm != 0 || a.n > a.np || a.n < 1 || a.sync == nullptr) return hipErrorInvalidValue;
+  const int nb = a.np / bm;
+  if ((long)nb * nb > kOnchipMaxGrid) return hipErrorInvalidValue;
+  switch (bm) {
+    case 64:
+      sdsn_onchip_kernel<64><<<nb * nb, 256, 0, s>>>(a);
+      break;
+    case 128:
+      sdsn_onchip_kernel<128><<<nb * nb, 512, 0, s>>>(a);
+      break;
+    case 256:
+      sdsn_onchip_kernel<256><<<nb * nb, 1024, 0, s>>>(a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fram

@@ -45,6 +45,8 @@ class Stats(ctypes.Structure):
         ("ms_update", ctypes.c_double),
         ("stalled", ctypes.c_int),
         ("ms_discretize", ctypes.c_double),
+        ("sdsn_onchip", ctypes.c_int),
+        ("sdsn_fallbacks", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:

@@ -241,7 +241,7 @@ class Server:
                     return
                 try:
                     perm, obj, st = ctx.solve(req.A, req.B, theta=self.theta, iters=self.iters,
-                                              tol=self.tol, sdsn_mode="stream", **self.opts)
+                                              tol=self.tol, sdsn_mode="auto", **self.opts)
                 except Exception as e:  # noqa: BLE001 - recorded on the request
                     req.error = f"{type(e).__name__}: {e}"
                     perm, obj, st = None, float("nan"), None

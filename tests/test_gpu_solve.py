@@ -225,7 +225,6 @@ def test_batched_mixed_sizes_and_tolerance(ctx):
     assert stats[2]["gemm_tile"] != 32
 
 
-@FAULT_SKIP
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n", [50, 700, 2100])
 def test_onchip_and_streaming_solves_agree(ctx, n, prec):
@@ -251,19 +250,21 @@ def test_stability_stop_matches_oracle(ctx, seed):
     assert abs(sb[0]["outer_iters"] - info.outer_iters) <= 2
 
 
-@FAULT_SKIP
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
 def test_n4000_stability_stop_accuracy_gate(ctx, prec):
-    # The n = 4000 workload with delta <= 1e-6 or a 3-iteration stable argmax:
-    # the low-precision paths level off above delta = 1e-6, the second rule
-    # stops them; the result must meet the accuracy gate against the oracle's
-    # delta-converged solve.
+    # The n = 4000 workload with delta <= 1e-6 or a 3-iteration stable argmax.
+    # On this pair the row argmax of N is never a permutation (outlier rows of
+    # B collide; the oracle's final row argmax is not one either), so the
+    # stability rule cannot fire and a low-precision run ends at the cap or on
+    # delta; either way the result must meet the accuracy gate against the
+    # oracle's delta-converged solve.
     g = _golden("fram_c2_seed2000.json")
+    assert not g["row_argmax_is_perm"]
     pr = next(synth.config_pairs(2, [0]))
     perm, obj, st = ctx.solve(pr.A, pr.B, theta=2.0, iters=100, tol=1e-6, prec=prec,
                               stable_iters=3)
     check_perm(perm, pr.n)
-    assert st["outer_iters"] < 100
+    assert st["outer_iters"] == 100 or st["delta"] <= 1e-6
     assert abs(obj - g["objective"]) <= 1e-3 * abs(g["objective"])
     assert O.accuracy(perm, pr.perm, pr.inlier) >= g["accuracy"] - 0.005
 
@@ -386,3 +387,19 @@ def test_warm_start_on_device_memory(ctx):
     np.testing.assert_array_equal(dN2.cpu().numpy(), N_ab)
     np.testing.assert_array_equal(p_b, p_ab)
     assert o_b == o_ab
+
+
+def test_concurrent_onchip_solves_equal_solving_alone(ctx):
+    # Several contexts (fram_solve_many's workers, one stream and host thread
+    # each) solving multi-tile pairs at once: their on-chip projections are
+    # launched one after another across the streams, and every result equals
+    # the streaming solve of that pair alone, bit for bit.
+    sizes = [600, 900, 1300, 1700, 2100, 2500]
+    pairs = [synth.make_pair(n, 0.3, 0.05, 5300 + n) for n in sizes]
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=20,
+                                        prec="bf16", many_workers=6)
+    for p, perm, obj, st in zip(pairs, perms, objs, stats):
+        p1, o1, s1 = ctx.solve(p.A, p.B, iters=20, prec="bf16", sdsn_mode="stream")
+        np.testing.assert_array_equal(perm, p1)
+        assert obj == o1 and st["sdsn_passes"] == s1["sdsn_passes"]
+        assert st["sdsn_onchip"] + st["sdsn_fallbacks"] == 20
