@@ -7,15 +7,20 @@ weights, permuted copy with N(0, 0.05) edge noise and 10% outlier nodes,
 seed 2000), with A and B resident in HBM before timing starts
 (fram_solve_dev).  The headline value is solves/s of the mixed-precision path
 (BF16 MFMA GEMMs, FP32 SDSN, FP64 gamma/delta/objective); the same pair is
-also timed with FP32 GEMMs, and one extra profiled solve of each precision
-gives per-kernel device times from HIP events on the library's stream.
+also timed with FP16 and with FP32 GEMMs.  The library records HIP events
+around its launches on the solve's stream during the timed solves (recorded,
+not waited for), which gives the per-kernel device times and the roofline of
+the dominant kernel.
 
-Two further legs can run after it (--batched, --serve):
-* batched: 512 independent pairs, n ~ U{20..300}, in one fram_solve_many call
-  (pairs/s, inputs uploaded inside the timed call);
-* served: Poisson arrivals at 200 requests/s for 30 s after a 5 s warm-up,
-  n log-uniform in [30, 2000], through the continuous-batching server
-  (p50 / p99 latency from arrival to result, completed requests/s).
+Further legs, each against the FP64 oracle timed on the host:
+* n = 50 (100 seeds, FP32 GEMMs, 100 fixed iterations) and n = 1000
+  (10 seeds, FP32, 100 fixed iterations): solves/s and agreement with the
+  oracle's permutations;
+* batched (--batched): 512 independent pairs, n ~ U{20..300}, in one
+  fram_solve_many call (pairs/s, inputs uploaded inside the timed call);
+* served (--serve): Poisson arrivals at 200 requests/s for 30 s after a 5 s
+  warm-up, n log-uniform in [30, 2000], through the continuous-batching
+  server (p50 / p99 latency from arrival to result, completed requests/s).
 
 Prints one JSON line.  Only one GPU is supported (--gpus 1).
 """
@@ -109,9 +114,53 @@ def measured_traffic(kind, n, passes_per_launch):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in ("sdsn_persistent.hip", "sdsn.hip", "sdsn_common.h"):
+    for name in ("sdsn_onchip.hip", "sdsn.hip", "sdsn_common.h"):
         h.update((ROOT / "paper_2508_00887_amd" / "csrc" / name).read_bytes())
     return h.hexdigest()
+
+
+def threads_used():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # noqa: BLE001
+        return os.cpu_count()
+
+
+def small_leg(ctx, config, seeds, cpu_seeds, cpu_iters):
+    """n = 50 (config 0) or n = 1000 (config 1) workload: FP32 GEMMs, 100
+    fixed outer iterations (tol = 0), every seed solved on the GPU from host
+    arrays (fram_solve_ex, uploads included); the FP64 oracle is timed on the
+    first `cpu_seeds` seeds with `cpu_iters` outer iterations and scaled to
+    100."""
+    import numpy as np
+    import synth
+    from oracle import fram64 as O
+    pairs = list(synth.config_pairs(config, list(range(seeds))))
+    ctx.solve(pairs[0].A, pairs[0].B, theta=THETA, iters=100, tol=0.0, prec="fp32")
+    t0 = time.perf_counter()
+    out = [ctx.solve(p.A, p.B, theta=THETA, iters=100, tol=0.0, prec="fp32") for p in pairs]
+    sec = (time.perf_counter() - t0) / len(pairs)
+    t0 = time.perf_counter()
+    same = 0
+    for p, (perm, _, _) in zip(pairs[:cpu_seeds], out):
+        s_or, _, _, _ = O.solve(p.A, p.B, theta=THETA, iters=cpu_iters)
+        if cpu_iters == 100:
+            same += int(np.array_equal(perm, s_or))
+    cpu = (time.perf_counter() - t0) / cpu_seeds * (100.0 / cpu_iters)
+    n = pairs[0].n
+    flops = 4.0 * n ** 3 * 100
+    return {
+        "n": n, "seeds": len(pairs), "solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec,
+        "gemm_tflop_per_s_effective": flops / sec / 1e12,
+        "mean_accuracy": float(np.mean([np.mean(o[0] == p.perm) for o, p in zip(out, pairs)])),
+        "oracle_permutation_equal": (f"{same}/{cpu_seeds}" if cpu_iters == 100 else None),
+        "gemm_precision": "fp32",
+        "cpu_baseline": {"value": 1.0 / cpu, "unit": "solves/s", "cores": int(threads_used()),
+                         "kind": "oracle",
+                         "sample": (f"FP64 oracle, {cpu_seeds} seed(s), {cpu_iters} outer "
+                                    f"iterations each, scaled to 100")},
+    }
 
 
 def batched_leg(Context, reps=2):
@@ -168,11 +217,13 @@ def served_leg(rate=200.0, duration_s=30.0, warmup_s=5.0, pool=160):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 50 and n = 1000 legs")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the second low-precision leg")
     ap.add_argument("--sdsn-mode", default="auto", choices=["auto", "stream", "onchip"])
     # The batched and served legs run only on request: fram_solve_many runs
     # pair by pair while the batched kernel is switched off.
@@ -255,6 +306,13 @@ def main():
     acc = float(np.mean((perm == pair.perm)[pair.inlier]))
     res = {}
     prof = {args.prec: pm}
+    other = "fp16" if args.prec == "bf16" else "bf16"
+    if not args.no_fp16:
+        sec16, (perm16, obj16, st16), prof[other] = timed(other, max(1, args.steps // 2), 1)
+        res[other] = dict(solves_per_s=1.0 / sec16, ms_per_solve=1e3 * sec16,
+                          outer_iters=st16["outer_iters"], sdsn_passes=st16["sdsn_passes"],
+                          objective=obj16,
+                          accuracy=float(np.mean((perm16 == pair.perm)[pair.inlier])))
     if not args.no_fp32:
         sec32, (perm32, obj32, st32), prof["fp32"] = timed("fp32", max(1, args.steps // 2), 1)
         res["fp32"] = dict(solves_per_s=1.0 / sec32, ms_per_solve=1e3 * sec32,
@@ -262,8 +320,8 @@ def main():
                            objective=obj32,
                            accuracy=float(np.mean((perm32 == pair.perm)[pair.inlier])))
     # Algorithmic bytes of one SDSN pass: read X and write Y once (8 n^2).  The
-    # on-chip variant runs a whole projection per launch and keeps X in VGPRs,
-    # so its effective rate can exceed the HBM roofline.
+    # on-chip kernel runs a whole projection per launch and keeps X on chip,
+    # so its streaming-equivalent rate can exceed the HBM roofline.
     pass_bytes = 8.0 * n * n
     bytes_per_launch = pass_bytes * pm["sdsn_passes"] / max(1, pm["sdsn_launches"])
     achieved = bytes_per_launch / (pm["sdsn_us_per_launch"] * 1e-6) / 1e9
@@ -294,7 +352,7 @@ def main():
         "gemm_tflops": {k: v["gemm_tflops"] for k, v in prof.items()},
         "profile": prof,
         "roofline": {"bound": "hbm",
-                     "kernel": "sdsn_persistent_kernel (one launch per projection)" if onchip
+                     "kernel": "sdsn_onchip_kernel<256> (one launch per projection)" if onchip
                      else "sdsn tile_kernel (one launch per pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -305,9 +363,22 @@ def main():
         "oracle_outer_iters": g["outer_iters"] if g else None,
         "stop_rule": {"tol": TOL, "stall_iters": STALL_ITERS, "iters_cap": ITERS},
     }
+    if other in res:
+        line[other] = res[other]
+        if g:
+            line[other]["rel_obj_err_vs_oracle"] = (abs(res[other]["objective"] - g["objective"])
+                                                    / abs(g["objective"]))
     if "fp32" in res:
         line["fp32"] = res["fp32"]
         line["speedup_vs_fp32"] = line["value"] / res["fp32"]["solves_per_s"]
+        if g:
+            line["fp32"]["rel_obj_err_vs_oracle"] = (abs(res["fp32"]["objective"] - g["objective"])
+                                                     / abs(g["objective"]))
+    if not args.no_small:
+        log("n = 50 leg (100 seeds)")
+        line["small_n50"] = small_leg(ctx, 0, 100, 20, 100)
+        log("n = 1000 leg (10 seeds)")
+        line["small_n1000"] = small_leg(ctx, 1, 10, 1, 10)
     if args.batched:
         log("batched leg: 512 pairs")
         line["batched"] = batched_leg(Context)
