@@ -255,6 +255,31 @@ fram_status fram_sdsn_project_dev(fram_ctx* ctx, const float* dK, int ldk, int n
                                   double lambda, const fram_options* opt, float* dX,
                                   int ldx, fram_stats* stats, void* stream);
 
+/* Largest n fram_sdsn_project_noalloc takes. */
+#define FRAM_NOALLOC_MAX_N 1024
+
+/* fram_sdsn_project_dev for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, and no allocation of any kind -- the working memory
+ * (padded iterate, tile partials, state; at most 6 MiB) is a file-scope device
+ * array of the library, one per GPU, held until the process ends.
+ *   dK, dX   device, n x n floats with leading dimensions ldk, ldx >= n
+ *            (dX may equal dK); n <= FRAM_NOALLOC_MAX_N (else FRAM_EINVAL).
+ *   opt      NULL = defaults; gamma_tol, sdsn_max and tile (0, 64 or 128) are
+ *            used; sdsn_mode 2 (on-chip) is FRAM_EINVAL: the streaming passes
+ *            always run, the same kernels as fram_sdsn_project_dev's
+ *            streaming mode, so X is the same bit for bit.
+ *   stats    NULL or written (sdsn_passes, gamma, sdsn_capped, gemm_tile).
+ *   stream   a hipStream_t (NULL = the default stream); the call returns after
+ *            the stream has finished the projection.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap
+ * on one GPU, from several threads or streams, race and must be serialised by
+ * the caller. */
+fram_status fram_sdsn_project_noalloc(const float* dK, int ldk, int n, double lambda,
+                                      const fram_options* opt, float* dX, int ldx,
+                                      fram_stats* stats, void* stream);
+
 /* Gradient of eq. (3) alone, for kernel checks: X = A * N * B computed as
  * W = B N^T (GEMM 1) and X = A W^T (GEMM 2) with inputs rounded to `prec`
  * and FP32 accumulation; W is held in `prec`.  All pointers are host, n*n,

@@ -100,6 +100,7 @@ _SIGS = {
     "fram_sdsn_project": (_I, [_P, _P, _I, _D, _P]),
     "fram_sdsn_project_ex": (_I, [_P, _P, _I, _D, _P, _P, _P]),
     "fram_sdsn_project_dev": (_I, [_P, _P, _I, _I, _D, _P, _P, _I, _P, _P]),
+    "fram_sdsn_project_noalloc": (_I, [_P, _I, _I, _D, _P, _P, _I, _P, _P]),
     "fram_gradient": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "fram_assign": (_I, [_P, _P, _I, _P]),
     "fram_assign_dev": (_I, [_P, _P, _I, _I, _P, _P]),
@@ -207,6 +208,19 @@ def fram_status_str(status: int) -> str:
 
 def fram_last_error(ctx: int) -> str:
     return load_library().fram_last_error(ctx).decode()
+
+
+def fram_sdsn_project_noalloc(dK: int, ldk: int, n: int, dX: int, ldx: int, theta=2.0,
+                              gamma_tol=1e-6, sdsn_max=1000, tile=0, stream=0) -> dict:
+    """fram_sdsn_project_noalloc on device pointers (no context); returns the
+    stats dict."""
+    stats = Stats()
+    o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile, False, "stream")
+    st = load_library().fram_sdsn_project_noalloc(dK, ldk, n, theta, ctypes.byref(o), dX, ldx,
+                                                  ctypes.byref(stats), stream or None)
+    if st != FRAM_OK:
+        raise FramError(st, "fram_sdsn_project_noalloc", fram_status_str(st))
+    return stats.as_dict()
 
 
 def _check(ctx: int, st: int, where: str):

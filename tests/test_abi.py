@@ -244,3 +244,25 @@ def test_warm_start_arguments_are_validated_before_device_use(hctx):
 def test_default_options_have_no_warm_start():
     o = F.fram_default_options()
     assert not o.N0 and not o.N_out
+
+
+def test_noalloc_projection_validates_before_any_device_call():
+    # fram_sdsn_project_noalloc: sizes above its scratch limit, the on-chip
+    # mode, a tile it does not hold and NULL pointers are refused on the host.
+    lib = F.load_library()
+    K = np.zeros((4, 4), dtype=np.float32)
+    p = K.ctypes.data
+
+    def call(n, ldk=None, mode="stream", tile=0, dk=p, dx=p, theta=2.0):
+        o = F._options("fp32", 0.95, 1e-6, 1000, tile, False, mode)
+        return lib.fram_sdsn_project_noalloc(dk, ldk or n, n, theta, ctypes.byref(o), dx,
+                                             ldk or n, None, None)
+
+    assert call(1025) == F.FRAM_EINVAL            # FRAM_NOALLOC_MAX_N = 1024
+    assert call(0) == F.FRAM_EINVAL
+    assert call(100, ldk=99) == F.FRAM_EINVAL
+    assert call(100, mode="onchip") == F.FRAM_EINVAL
+    assert call(100, tile=256) == F.FRAM_EINVAL
+    assert call(100, dk=None) == F.FRAM_EINVAL
+    assert call(100, dx=None) == F.FRAM_EINVAL
+    assert call(100, theta=0.0) == F.FRAM_EINVAL
