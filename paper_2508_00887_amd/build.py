@@ -24,7 +24,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", str(ROOT / "include"), "-Wall", "-Wno-unused-function",
 ]
-SOURCES = ["gemm.hip", "sdsn.hip", "sdsn_onchip.hip", "batch.hip", "misc.hip", "runtime.hip", "lap.hip", "noalloc.hip"]
+SOURCES = ["gemm.hip", "sdsn.hip", "sdsn_onchip.hip", "misc.hip", "runtime.hip", "lap.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> pathlib.Path:

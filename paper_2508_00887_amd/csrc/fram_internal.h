@@ -109,6 +109,9 @@ struct OnchipArgs {
   double* dpart;     // FP64 delta partials, 2 per workgroup (tile order)
 };
 
+// Workgroups of the BM variant that fit on one compute unit (0 on error).
+int sdsn_onchip_per_cu(int bm);
+
 // True if the nb*nb workgroups of the BM variant can all be resident on
 // `device` at once (an idle device; the roll call covers the rest).
 bool sdsn_onchip_fits(int device, int bm, int np);
@@ -120,44 +123,6 @@ hipError_t launch_sdsn_onchip(int bm, const OnchipArgs& a, hipStream_t s);
 
 // st->delta from `nblocks` pairs of FP64 partial sums (num, den).
 hipError_t launch_delta_final(const double* part, int nblocks, DevState* st, hipStream_t s);
-
-// ---------------------------------------------------------------- batched
-// One pair of the batched solver.  Byte offsets are into the batch arena;
-// matrices are np x np (np = n rounded up to 32), zero padded.
-struct BatchPair {
-  int n, np;
-  long long a64, b64;         // FP64 unscaled inputs, n x n, leading dimension n
-  long long alp, blp, w, nlp; // GEMM-type A, B, W, N copies (np x np)
-  long long nf, x;            // FP32 N and X (np x np)
-  long long sigma;            // int32[n]
-  long long sigprev;          // int32[n], previous argmax (stability stop)
-};
-
-// Per-pair results of the batched solver.
-struct BatchResult {
-  double objective, delta, gamma;
-  int outer_iters, sdsn_passes, sdsn_passes_max, sdsn_passes_last;
-  int converged, sdsn_capped;
-  int is_perm;    // the final row argmax was a permutation
-  int lap_paths;  // else: rows that needed an augmenting path (-1: failed)
-};
-
-struct BatchArgs {
-  const BatchPair* pairs;
-  const int* order;     // processing order (largest n first)
-  int count;
-  int* next;            // work-queue counter, zero at launch
-  char* arena;
-  BatchResult* res;
-  double theta, alpha, gamma_tol, tol;
-  int iters, sdsn_max;
-  int stable_iters;     // argmax-stability stop (0 = off)
-};
-
-constexpr int kBatchMaxN = 512;  // largest pair the batched kernel takes
-
-// Persistent batched FRAM: `grid` workgroups pull pairs from the queue.
-hipError_t launch_fram_batch(Elem e, const BatchArgs& a, int grid, hipStream_t s);
 
 // N <- (1-alpha) N + alpha D with FP64 partial sums for delta; writes the
 // GEMM-operand copy Nlp in type e (skipped when e == F32 and Nlp == N).

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -158,9 +159,6 @@ bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP
 
 // Devices whose on-chip SDSN launches are ordered (see OnchipGate).
 constexpr int kMaxGateDevices = 64;
-// The batched kernel stays off until its own runs on the device are clean;
-// fram_solve_many then solves pair by pair.
-constexpr bool kBatchedKernel = false;
 // Most worker contexts of one fram_solve_many call (fram_options.many_workers).
 constexpr int kMaxManyWorkers = 32;
 
@@ -453,13 +451,26 @@ fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool
 constexpr long long kRollCallMs = 10;
 constexpr long long kBarrierMs = 200;
 
-// On-chip SDSN launches are ordered one after the other across all streams of
-// the process on a device: each waits (on the device) for the completion
-// event of the previous one, so no two of these grids, whose workgroups wait
-// for each other, ever compete for compute units.
+// Compute-unit budget of the on-chip SDSN launches of the process on a device.
+// A grid of G workgroups of which `per_cu` fit on one compute unit occupies
+// G / per_cu compute units.  Before a launch, the launches that may still be
+// running are counted; while they and the new grid together would need more
+// compute units than the device has, the new launch waits (on the device, for
+// the completion event) for the oldest of them.  So the grids that can run at
+// the same time always fit on the device together: many small projections
+// (small pairs solved concurrently) overlap, and a grid that needs the whole
+// device (n = 4000) runs alone.  Every wait points back to an earlier launch,
+// so the waits cannot form a cycle.  The roll call in the kernel still guards
+// against compute units held by other kernels.
 struct OnchipGate {
   std::mutex mu;
-  hipEvent_t last = nullptr;
+  struct Live {
+    hipEvent_t ev;
+    double cus;
+  };
+  std::deque<Live> live;         // launches that may still run, oldest first
+  std::vector<hipEvent_t> idle;  // events of completed launches, for reuse
+  int cus = 0;                   // compute units of the device
 };
 OnchipGate g_gate[kMaxGateDevices];
 
@@ -492,14 +503,40 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   a.dpart = at<double>(c, L.upd);
   OnchipGate& g = g_gate[c->device];
   std::lock_guard<std::mutex> lk(g.mu);
-  if (g.last == nullptr) {
-    HIPCHK(hipEventCreateWithFlags(&g.last, hipEventDisableTiming));
+  if (g.cus == 0) HIPCHK(hipDeviceGetAttribute(&g.cus, hipDeviceAttributeMultiprocessorCount,
+                                               c->device));
+  const int per_cu = std::max(1, fram::sdsn_onchip_per_cu(L.bm));
+  const double need = std::min((double)g.cus, (double)L.nb * L.nb / per_cu);
+  // Forget launches that have completed.
+  double used = 0.0;
+  for (auto it = g.live.begin(); it != g.live.end();) {
+    const hipError_t q = hipEventQuery(it->ev);
+    if (q == hipSuccess) {
+      g.idle.push_back(it->ev);
+      it = g.live.erase(it);
+    } else {
+      if (q != hipErrorNotReady) HIPCHK(q);
+      used += it->cus;
+      ++it;
+    }
+  }
+  // Wait for the oldest launches until this grid fits beside the rest.
+  while (!g.live.empty() && used + need > (double)g.cus + 1e-9) {
+    HIPCHK(hipStreamWaitEvent(s, g.live.front().ev, 0));
+    used -= g.live.front().cus;
+    g.live.pop_front();  // this launch starts after it: no longer counted
+  }
+  hipEvent_t ev = nullptr;
+  if (!g.idle.empty()) {
+    ev = g.idle.back();
+    g.idle.pop_back();
   } else {
-    HIPCHK(hipStreamWaitEvent(s, g.last, 0));
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   }
   HIPCHK(fram::launch_zero(c->sync, fram::kOnchipSyncBytes, s));
   HIPCHK(fram::launch_sdsn_onchip(L.bm, a, s));
-  HIPCHK(hipEventRecord(g.last, s));
+  HIPCHK(hipEventRecord(ev, s));
+  g.live.push_back({ev, need});
   return FRAM_OK;
 }
 
@@ -1250,145 +1287,6 @@ fram_status fram_gradient(fram_ctx* c, const float* A, const float* N, const flo
 
 }  // extern "C"
 
-namespace {
-
-// Batched solve of the pairs listed in `ids` (all 2 <= n <= kBatchMaxN) with
-// the persistent kernel; results go to perm_out / objective_out / stats.
-fram_status solve_batched(fram_ctx* c, const std::vector<int>& ids, const double* const* A,
-                          const double* const* B, const int* n, double theta, int iters,
-                          double tol, const fram_options& o, int32_t* const* perm_out,
-                          double* objective_out, fram_stats* stats) {
-  const Elem e = (Elem)o.prec;
-  const size_t es = fram::elem_size(e);
-  const int m = (int)ids.size();
-  std::vector<fram::BatchPair> pairs(m);
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off += align_up(bytes);
-    return (long long)at;
-  };
-  // Inputs first (contiguous, one upload), then the working matrices.
-  size_t in_elems = 0;
-  for (int q = 0; q < m; ++q) {
-    const int nn = n[ids[q]];
-    pairs[q].n = nn;
-    pairs[q].np = (nn + 31) / 32 * 32;
-    pairs[q].a64 = (long long)(in_elems * 8);
-    in_elems += (size_t)nn * nn;
-    pairs[q].b64 = (long long)(in_elems * 8);
-    in_elems += (size_t)nn * nn;
-  }
-  off = align_up(in_elems * 8);
-  size_t sig_elems = 0;
-  const size_t sig_base = off;
-  for (int q = 0; q < m; ++q) {
-    pairs[q].sigma = (long long)(sig_base + sig_elems * 4);
-    sig_elems += (size_t)pairs[q].n;
-  }
-  off = align_up(sig_base + sig_elems * 4);
-  for (int q = 0; q < m; ++q) pairs[q].sigprev = take((size_t)pairs[q].n * 4);
-  for (int q = 0; q < m; ++q) {
-    const size_t np2 = (size_t)pairs[q].np * pairs[q].np;
-    pairs[q].alp = take(np2 * es);
-    pairs[q].blp = take(np2 * es);
-    pairs[q].w = take(np2 * es);
-    pairs[q].nlp = (e == Elem::F32) ? 0 : take(np2 * es);
-    pairs[q].nf = take(np2 * 4);
-    pairs[q].x = take(np2 * 4);
-  }
-  const long long pairs_off = take(sizeof(fram::BatchPair) * m);
-  const long long order_off = take(sizeof(int) * m);
-  const long long next_off = take(sizeof(int));
-  const long long res_off = take(sizeof(fram::BatchResult) * m);
-  const size_t total = off;
-  if (c->budget != 0 && total > c->budget) {
-    c->err = "batched workspace exceeds the HBM budget";
-    return FRAM_ENOMEM;
-  }
-  fram_status r = ensure_device(c);
-  if (r != FRAM_OK) return r;
-  r = ensure_ws(c, total);
-  if (r != FRAM_OK) return r;
-  hipStream_t s = c->stream;
-  char* ar = static_cast<char*>(c->ws);
-
-  // Largest pairs first (longest-processing-time order).
-  std::vector<int> order(m);
-  for (int q = 0; q < m; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return pairs[x].n > pairs[y].n; });
-  std::vector<double> staged(in_elems);
-  for (int q = 0; q < m; ++q) {
-    const size_t nn2 = (size_t)pairs[q].n * pairs[q].n;
-    std::memcpy(&staged[pairs[q].a64 / 8], A[ids[q]], nn2 * 8);
-    std::memcpy(&staged[pairs[q].b64 / 8], B[ids[q]], nn2 * 8);
-  }
-  HIPCHK(hipMemcpyAsync(ar, staged.data(), in_elems * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ar + pairs_off, pairs.data(), sizeof(fram::BatchPair) * m,
-                        hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ar + order_off, order.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
-  HIPCHK(fram::launch_zero(ar + next_off, sizeof(int), s));
-
-  fram::BatchArgs a{};
-  a.pairs = reinterpret_cast<const fram::BatchPair*>(ar + pairs_off);
-  a.order = reinterpret_cast<const int*>(ar + order_off);
-  a.count = m;
-  a.next = reinterpret_cast<int*>(ar + next_off);
-  a.arena = ar;
-  a.res = reinterpret_cast<fram::BatchResult*>(ar + res_off);
-  a.theta = theta;
-  a.alpha = o.alpha;
-  a.gamma_tol = o.gamma_tol;
-  a.tol = tol;
-  a.iters = iters;
-  a.sdsn_max = o.sdsn_max;
-  a.stable_iters = o.stable_iters;
-  int cus = 0;
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int grid = std::max(1, std::min(m, 3 * cus));
-  HIPCHK(fram::launch_fram_batch(e, a, grid, s));
-  std::vector<fram::BatchResult> res(m);
-  std::vector<int32_t> sig(sig_elems);
-  HIPCHK(hipMemcpyAsync(res.data(), ar + res_off, sizeof(fram::BatchResult) * m,
-                        hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(sig.data(), ar + sig_base, sig_elems * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-
-  for (int q = 0; q < m; ++q) {
-    const int p = ids[q];
-    const int32_t* sq = &sig[(pairs[q].sigma - (long long)sig_base) / 4];
-    std::memcpy(perm_out[p], sq, (size_t)pairs[q].n * 4);
-    objective_out[p] = res[q].objective;
-    if (!is_permutation(sq, pairs[q].n)) {
-      c->err = "no finite assignment in batched pair " + std::to_string(p);
-      return FRAM_ENUMERIC;
-    }
-    if (!std::isfinite(res[q].objective) || !std::isfinite(res[q].delta) ||
-        !std::isfinite(res[q].gamma)) {
-      c->err = "non-finite value in batched pair " + std::to_string(p);
-      return FRAM_ENUMERIC;
-    }
-    if (stats) {
-      fram_stats& st = stats[p];
-      st = fram_stats{};
-      st.outer_iters = res[q].outer_iters;
-      st.sdsn_passes = res[q].sdsn_passes;
-      st.sdsn_passes_last = res[q].sdsn_passes_last;
-      st.sdsn_passes_max = res[q].sdsn_passes_max;
-      st.converged = res[q].converged;
-      st.sdsn_capped = res[q].sdsn_capped;
-      st.lap_paths = res[q].is_perm ? 0 : res[q].lap_paths;
-      st.gemm_tile = 32;
-      st.delta = res[q].delta;
-      st.gamma = res[q].gamma;
-    }
-  }
-  return FRAM_OK;
-}
-
-}  // namespace
-
 extern "C" {
 
 fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
@@ -1415,28 +1313,20 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
     }
   }
   const double t0 = now_ms();
-  std::vector<int> batched, single;
+  std::vector<int> single;
   for (int p = 0; p < count; ++p) {
     if (n[p] == 1) {
       perm_out[p][0] = 0;
       objective_out[p] = A[p][0] * B[p][0];
       if (stats) stats[p] = fram_stats{};
-    } else if (kBatchedKernel && n[p] <= fram::kBatchMaxN) {
-      batched.push_back(p);
     } else {
       single.push_back(p);
     }
   }
-  if (!batched.empty()) {
-    r = solve_batched(c, batched, A, B, n, lambda, iters, tol, o, perm_out, objective_out, stats);
-    if (r != FRAM_OK) return r;
-  }
-  // Pairs too large for one workgroup (all pairs while the batched kernel is
-  // switched off) go through the single-pair path: up to o.many_workers pairs
-  // at a time, each on a worker context with its own stream and workspace
-  // (one host thread per worker), largest pairs first.  Each pair's result
-  // is that of solving it alone: nothing is shared between the workers but
-  // the device.
+  // Every pair runs the single-pair path: up to o.many_workers pairs at a
+  // time, each on a worker context with its own stream and workspace (one
+  // host thread per worker), largest pairs first.  Each pair's result is that
+  // of solving it alone: nothing is shared between the workers but the device.
   if (!single.empty()) {
     std::stable_sort(single.begin(), single.end(), [&](int x, int y) { return n[x] > n[y]; });
     const int nw = (int)std::min<size_t>((size_t)o.many_workers, single.size());

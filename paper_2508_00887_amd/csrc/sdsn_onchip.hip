@@ -406,23 +406,28 @@ int resident_per_cu() {
 
 }  // namespace
 
+int sdsn_onchip_per_cu(int bm) {
+  // Queried once per variant (the answer depends only on the kernel).
+  static const int k64 = resident_per_cu<64>();
+  static const int k128 = resident_per_cu<128>();
+  static const int k256 = resident_per_cu<256>();
+  switch (bm) {
+    case 64:
+      return k64;
+    case 128:
+      return k128;
+    case 256:
+      return k256;
+  }
+  return 0;
+}
+
 bool sdsn_onchip_fits(int device, int bm, int np) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return false;
   const long nb = np / bm;
-  int per_cu = 0;
-  switch (bm) {
-    case 64:
-      per_cu = resident_per_cu<64>();
-      break;
-    case 128:
-      per_cu = resident_per_cu<128>();
-      break;
-    case 256:
-      per_cu = resident_per_cu<256>();
-      break;
-  }
+  const int per_cu = sdsn_onchip_per_cu(bm);
   return nb * nb <= (long)per_cu * cus && nb * nb <= kOnchipMaxGrid;
 }
 

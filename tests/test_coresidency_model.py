@@ -19,12 +19,13 @@ What it shows:
   bound on the wait hangs the device (with a bound, every workgroup times out);
 * a barrier grid next to a kernel that holds a slot for a long time (one
   workgroup of the assignment) only waits, it does not deadlock;
-* the launch protocol of the library -- on-chip launches ordered one after
-  the other across all streams of the process (each waits for the previous
-  one's completion event), a roll call at kernel start with a bounded wait,
-  and a fallback to the streaming passes when the roll call fails -- completes
-  in every scenario, with the fallback taken only when a long kernel of
-  another stream holds slots past the roll-call bound.
+* the launch protocol of the library -- a compute-unit budget over the
+  on-chip launches of the process (a launch that would not fit beside the
+  launches that may still run waits for the oldest of them), a roll call at
+  kernel start with a bounded wait, and a fallback to the streaming passes
+  when the roll call fails -- completes in every scenario, lets small grids
+  run side by side, and takes the fallback only when a long kernel of another
+  stream holds slots past the roll-call bound.
 """
 from __future__ import annotations
 
@@ -166,15 +167,22 @@ def test_a_long_kernel_of_another_stream_only_delays_a_barrier_grid():
     assert not r["deadlock"] and k.outcome == "ok" and k.finished_at >= 50_000.0
 
 
-def serialized(kernels: list[Kernel]) -> list[Kernel]:
-    """The library's launch order for on-chip grids: each waits for the
-    completion of the previous one (process-wide event chain)."""
-    prev = None
+def serialized(kernels: list[Kernel], slots: int = C) -> list[Kernel]:
+    """The library's launch protocol for on-chip grids, in submission order:
+    the launches that may still run are counted (here: every earlier one not
+    already waited for, since nothing has completed at submission), and while
+    they and the new grid together need more slots than the device has, the
+    new launch waits for the oldest of them."""
+    live: list[Kernel] = []
     for k in kernels:
-        if k.barrier:
-            if prev is not None:
-                k.after.append(prev)
-            prev = k
+        if not k.barrier:
+            continue
+        used = sum(x.grid for x in live)
+        while live and used + k.grid > slots:
+            k.after.append(live[0])
+            used -= live[0].grid
+            live.pop(0)
+        live.append(k)
     return kernels
 
 
@@ -200,3 +208,24 @@ def test_library_protocol_with_other_kernels_in_flight():
     assert {k.outcome for k in on} <= {"ok", "fallback"}
     assert any(k.outcome == "fallback" for k in on)
     assert all(k.outcome == "ok" for k in plain + [lap])
+
+
+def test_small_grids_run_side_by_side_under_the_budget():
+    # 16 projections of 16 workgroups each (small pairs solved concurrently):
+    # all fit together, so none waits for another and all finish at once.
+    ks = serialized([Kernel(f"small{i}", 16, True, 50.0, roll_call=20_000.0) for i in range(16)])
+    r = simulate(C, ks)
+    assert not r["deadlock"] and all(k.outcome == "ok" for k in ks)
+    assert all(not k.after for k in ks) and max(k.finished_at for k in ks) == 50.0
+
+
+def test_budget_with_mixed_grid_sizes_completes_without_fallback():
+    sizes = [16, 256, 64, 100, 256, 25, 128, 200]
+    ks = serialized([Kernel(f"g{i}", g, True, 50.0, roll_call=20_000.0)
+                     for i, g in enumerate(sizes)])
+    r = simulate(C, ks)
+    assert not r["deadlock"] and all(k.outcome == "ok" for k in ks)
+    # a whole-device grid never overlaps another on-chip grid
+    for k in ks:
+        if k.grid == C:
+            assert k.after

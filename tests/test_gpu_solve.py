@@ -18,10 +18,17 @@ import pytest
 import synth
 from oracle import fram64 as O
 
-from conftest import FAULT_SKIP
-
 pytestmark = pytest.mark.gpu
 GOLDEN = pathlib.Path(__file__).resolve().parent / "golden"
+
+# The batched kernel (one workgroup per pair, fram_solve_many for n <= 512)
+# made a GPU memory access fault on its first test run on the device
+# (8 pairs, FP32); a CPU emulation of the same launch finds no
+# out-of-bounds access, so the cause is not shown and the kernel stays
+# switched off.  These tests expect the batched kernel (gemm_tile 32).
+BATCHED_OFF = pytest.mark.skip(
+    reason="batched kernel switched off: it faulted the GPU on its first run and the cause "
+           "is not found (a CPU emulation of the launch runs clean)")
 
 
 def host_objective(A, B, perm):
@@ -177,7 +184,7 @@ def _small_batch(count, seed, n_hi=160):
                             seed * 1000 + i) for i in range(count)]
 
 
-@FAULT_SKIP
+@BATCHED_OFF
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_batched_pairs_match_oracle(ctx, prec):
     # The batched kernel (one workgroup per pair) against the FP64 oracle:
@@ -198,7 +205,7 @@ def test_batched_pairs_match_oracle(ctx, prec):
             assert O.accuracy(perm, pr.perm) >= O.accuracy(s_or, pr.perm) - 0.005
 
 
-@FAULT_SKIP
+@BATCHED_OFF
 def test_batched_result_is_the_same_alone_and_in_the_mix(ctx):
     pairs = _small_batch(40, 32, n_hi=300)
     perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=40)
@@ -209,7 +216,7 @@ def test_batched_result_is_the_same_alone_and_in_the_mix(ctx):
         assert s1[0]["sdsn_passes"] == stats[q]["sdsn_passes"]
 
 
-@FAULT_SKIP
+@BATCHED_OFF
 def test_batched_mixed_sizes_and_tolerance(ctx):
     # n = 1 is answered on the host, n > 512 goes through the single-pair path.
     big = synth.make_pair(600, 0.3, 0.05, 6060)
@@ -403,3 +410,18 @@ def test_concurrent_onchip_solves_equal_solving_alone(ctx):
         np.testing.assert_array_equal(perm, p1)
         assert obj == o1 and st["sdsn_passes"] == s1["sdsn_passes"]
         assert st["sdsn_onchip"] + st["sdsn_fallbacks"] == 20
+
+
+@BATCHED_OFF
+def test_batched_honours_the_stall_rule(ctx):
+    # BF16 delta levels off near 1e-4, far above tol = 1e-9: the delta-stall
+    # rule (the single-pair path's) ends every pair before the cap, and the
+    # result still meets the accuracy gate against the FP64 oracle.
+    pairs = _small_batch(6, 34, n_hi=250)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=100,
+                                        tol=1e-9, prec="bf16", stall_iters=3)
+    for pr, perm, obj, st in zip(pairs, perms, objs, stats):
+        assert st["gemm_tile"] == 32 and st["stalled"] == 1 and st["outer_iters"] < 100
+        s_or, obj_or, _, _ = O.solve(pr.A, pr.B, iters=100, tol=1e-9)
+        assert abs(obj - obj_or) <= 1e-3 * abs(obj_or)
+        assert O.accuracy(perm, pr.perm) >= O.accuracy(s_or, pr.perm) - 0.005
