@@ -145,9 +145,10 @@ typedef struct {
   int dsn_iters;         /* DSPFP projection passes per outer iteration; default 30     */
   int many_workers;      /* fram_solve_many: pairs solved at the same time, each on a
                             worker context with its own stream (one host thread each);
-                            1..32, default 8.  Measured on 512 pairs of n in [20, 300]:
-                            8 workers 90 pairs/s, 4 workers 83; with the default 4
-                            hardware queues per process (more queues were slower)     */
+                            1..32, default 16.  Streams share the process's hardware
+                            queues (HIP's GPU_MAX_HW_QUEUES, read when HIP starts):
+                            measured on 512 pairs of n in [20, 300], 16 workers give
+                            115 pairs/s with 4 queues and 216 with 16              */
   const float* N0;       /* warm start of Algorithm 1 step 1: NULL (default) starts from
                             N = 0; else n*n floats, row-major, finite, used as N^(0)
                             (host memory for the host entry points, device memory with

@@ -446,10 +446,11 @@ fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool
 // Bounds on the waits of the on-chip SDSN.  The roll call (all workgroups
 // resident) normally completes within microseconds; when kernels of other
 // streams hold compute units longer than this, the launch is abandoned and
-// the projection streams instead.  A pass barrier takes a few microseconds,
-// so its bound only ends a launch that can no longer complete.
+// the projection streams instead.  A pass barrier takes a few microseconds;
+// its bound (long enough to ride out a time slice of the queue) only ends a
+// launch that can no longer complete.
 constexpr long long kRollCallMs = 10;
-constexpr long long kBarrierMs = 200;
+constexpr long long kBarrierMs = 2000;
 
 // Compute-unit budget of the on-chip SDSN launches of the process on a device.
 // A grid of G workgroups of which `per_cu` fit on one compute unit occupies
@@ -959,7 +960,7 @@ void fram_default_options(fram_options* opt) {
   opt->stall_delta = 1e-3;
   opt->variant = 0;
   opt->dsn_iters = 30;
-  opt->many_workers = 8;
+  opt->many_workers = 16;
   opt->N0 = nullptr;
   opt->N_out = nullptr;
 }

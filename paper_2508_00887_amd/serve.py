@@ -102,8 +102,8 @@ class Budget:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 3,
-                 small_workers: int = 5, small_n: int = 512, prec: str = "bf16",
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 4,
+                 small_workers: int = 8, small_n: int = 512, prec: str = "bf16",
                  theta: float = 2.0, iters: int = 100, tol: float = 1e-6,
                  stall_iters: int = 3, device: int = 0, context_factory=None):
         if large_workers < 1 or small_workers < 0:
@@ -283,6 +283,7 @@ def summarize(done: list[Request], warmup_s: float, duration_s: float,
     return dict(
         requests=len(meas),
         failed=len(after) - len(meas),
+        errors=sorted({r.error for r in after if r.error})[:5],
         unfinished=(offered - len(after)) if offered is not None else 0,
         p50_ms=float(np.percentile(lat, 50)),
         p99_ms=float(np.percentile(lat, 99)),
