@@ -35,10 +35,27 @@ import time
 
 ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
+
+
+def _hw_queues_from_argv(argv, default=16):
+    """--hw-queues N (1..32), read before anything starts HIP."""
+    q = default
+    for i, a in enumerate(argv):
+        if a == "--hw-queues" and i + 1 < len(argv):
+            q = int(argv[i + 1])
+        elif a.startswith("--hw-queues="):
+            q = int(a.split("=", 1)[1])
+    if not 1 <= q <= 32:
+        raise SystemExit("--hw-queues must be between 1 and 32")
+    return q
+
+
 # The batched and served legs run many solves at once, one stream each; HIP
 # maps a process's streams onto GPU_MAX_HW_QUEUES hardware queues, read when
-# HIP starts (before the first device call below).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# HIP starts (before the first device call below).  The benchmark sets the
+# count itself (an inherited value would otherwise decide the concurrent legs).
+HW_QUEUES = _hw_queues_from_argv(sys.argv[1:])
+os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 
 N_WORKLOAD = 4000
@@ -247,6 +264,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-pair leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32")
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="offered requests/s of the served leg (the served workload: 200)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,7 +381,8 @@ def main():
                                "10% outliers, seed 2000",
                    "n": n, "theta": THETA, "iters_cap": ITERS, "tol": TOL,
                    "stall_iters": STALL_ITERS, "gamma_tol": GAMMA_TOL,
-                   "gemm_precision": args.prec, "sdsn_mode": args.sdsn_mode},
+                   "gemm_precision": args.prec, "sdsn_mode": args.sdsn_mode,
+                   "hw_queues": HW_QUEUES},
         "outer_iters": st["outer_iters"], "sdsn_passes": st["sdsn_passes"],
         "accuracy": acc, "objective": obj, "rel_obj_err_vs_oracle": rel_err,
         "lap_paths": st["lap_paths"],

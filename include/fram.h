@@ -101,9 +101,13 @@ typedef struct {
   double ms_discretize;  /* (profile 1 or 2) Algorithm 1 step 10 on the device: row
                             argmax, column minima and the exact assignment           */
   int sdsn_onchip;       /* projections run by the on-chip SDSN launch                 */
-  int sdsn_fallbacks;    /* on-chip launches whose workgroups could not all be resident
-                            at once (compute units held by other work past a 10 ms
-                            bound): nothing was done and the projection streamed     */
+  int sdsn_fallbacks;    /* on-chip launches that did not complete, and whose
+                            projection therefore streamed (same result): either not
+                            all workgroups became resident within the roll-call bound
+                            (compute units held by other work), or a pass barrier
+                            waited past its bound (e.g. the launch's hardware queue
+                            was preempted) and the launch was abandoned before it
+                            wrote anything                                          */
 } fram_stats;
 
 typedef struct {
@@ -124,12 +128,14 @@ typedef struct {
                             on-chip: all passes of a projection (and, in solves, the N
                             update of Algorithm 1 step 7) in one launch with the
                             iterate held in registers (FRAM_EINVAL if the device cannot
-                            hold it).  On-chip launches are ordered one after another
-                            across all contexts and streams of the process; one whose
-                            workgroups cannot all be resident within 10 ms (compute
-                            units held by other work) does nothing and that projection
-                            streams instead (fram_stats.sdsn_fallbacks).  Both modes
-                            give the same iterates bit for bit.                        */
+                            hold it).  On-chip launches of all contexts and streams
+                            of the process are admitted only while the grids that may
+                            still run fit on the device together; one whose workgroups
+                            cannot all be resident within the roll-call bound, or
+                            whose pass barrier waits past its bound, writes nothing
+                            and that projection streams instead
+                            (fram_stats.sdsn_fallbacks).  Both modes give the same
+                            iterates bit for bit.                                    */
   int stall_iters;       /* w > 0: also stop once delta has stalled at the precision's
                             floor: after delta <= stall_delta, w consecutive iterations
                             without a new smallest delta; 0 = off (default)            */
@@ -161,6 +167,13 @@ typedef struct {
   float* N_out;          /* NULL (default) or n*n floats (same memory kind as N0): the
                             final iterate N, before discretisation (not written for
                             n = 1, which needs no iteration)                          */
+  int onchip_roll_us;    /* bound on the roll call of an on-chip launch (all workgroups
+                            resident), microseconds; 0 = default (10 000)            */
+  int onchip_barrier_us; /* bound on each pass barrier wait of an on-chip launch,
+                            microseconds; 0 = default (20 000).  A pass takes a few
+                            microseconds; the bound only ends a launch that has
+                            stopped progressing.  Tiny bounds force the fallbacks
+                            (same results), e.g. in tests                            */
 } fram_options;
 
 /* Sizes of fram_options and fram_stats as compiled into the library, for

@@ -161,6 +161,8 @@ bool valid_prec(int p) { return p == FRAM_FP32 || p == FRAM_BF16 || p == FRAM_FP
 constexpr int kMaxGateDevices = 64;
 // Most worker contexts of one fram_solve_many call (fram_options.many_workers).
 constexpr int kMaxManyWorkers = 32;
+// Largest accepted on-chip wait bound (fram_options.onchip_*_us): one minute.
+constexpr int kMaxOnchipWaitUs = 60000000;
 
 fram_status check_options(const fram_options& o) {
   if (!valid_prec((int)o.prec)) return FRAM_EINVAL;
@@ -176,6 +178,8 @@ fram_status check_options(const fram_options& o) {
   if (o.variant != 0 && o.variant != 1) return FRAM_EINVAL;
   if (o.dsn_iters < 1) return FRAM_EINVAL;
   if (o.many_workers < 1 || o.many_workers > kMaxManyWorkers) return FRAM_EINVAL;
+  if (o.onchip_roll_us < 0 || o.onchip_roll_us > kMaxOnchipWaitUs) return FRAM_EINVAL;
+  if (o.onchip_barrier_us < 0 || o.onchip_barrier_us > kMaxOnchipWaitUs) return FRAM_EINVAL;
   return FRAM_OK;
 }
 
@@ -443,14 +447,18 @@ fram_status use_onchip(fram_ctx* c, const Layout& L, const fram_options& o, bool
   return FRAM_OK;
 }
 
-// Bounds on the waits of the on-chip SDSN.  The roll call (all workgroups
-// resident) normally completes within microseconds; when kernels of other
-// streams hold compute units longer than this, the launch is abandoned and
-// the projection streams instead.  A pass barrier takes a few microseconds;
-// its bound (long enough to ride out a time slice of the queue) only ends a
-// launch that can no longer complete.
-constexpr long long kRollCallMs = 10;
-constexpr long long kBarrierMs = 2000;
+// Default bounds on the waits of the on-chip SDSN (fram_options.onchip_*_us
+// override them).  The roll call (all workgroups resident) normally completes
+// within microseconds; when kernels of other streams hold compute units
+// longer than this, the launch is abandoned and the projection streams
+// instead.  A pass barrier takes a few microseconds; a wait thousands of
+// times longer means a workgroup has stopped running (its hardware queue was
+// preempted, which happens when a process's queues outnumber those the
+// device schedules at once), and the grid gives up, writes nothing and the
+// projection streams: holding the other compute units until the queue
+// returns would only stall everything else.
+constexpr long long kRollCallUs = 10000;
+constexpr long long kBarrierUs = 20000;
 
 // Compute-unit budget of the on-chip SDSN launches of the process on a device.
 // A grid of G workgroups of which `per_cu` fit on one compute unit occupies
@@ -492,8 +500,9 @@ fram_status run_sdsn_onchip(fram_ctx* c, const Layout& L, int n, const float* sr
   a.p[1] = partials(c, L, 1);
   a.st = st;
   a.sync = c->sync;
-  a.roll_ticks = c->clock_khz * kRollCallMs;
-  a.wait_ticks = c->clock_khz * kBarrierMs;
+  a.roll_ticks = c->clock_khz * (o.onchip_roll_us > 0 ? o.onchip_roll_us : kRollCallUs) / 1000;
+  a.wait_ticks =
+      c->clock_khz * (o.onchip_barrier_us > 0 ? o.onchip_barrier_us : kBarrierUs) / 1000;
   a.max_passes = o.sdsn_max;
   a.theta = theta;
   a.gamma_tol = o.gamma_tol;
@@ -722,11 +731,9 @@ fram_status run_solve(fram_ctx* c, const Layout& L, const double* dA, const doub
       if (r != FRAM_OK) return r;
       r = read_state(c, st, s);
       if (r != FRAM_OK) return r;
-      if (c->hst->invalid & fram::kInvalidBarrier) {
-        c->err = "on-chip SDSN barrier timed out";
-        return FRAM_EDEVICE;
-      }
-      if (c->hst->invalid & fram::kInvalidRollCall) {
+      if (c->hst->invalid & (fram::kInvalidRollCall | fram::kInvalidBarrier)) {
+        // The launch wrote neither X nor N: stream this iteration's
+        // projection from the same X.
         HIPCHK(fram::launch_zero(&st->invalid, sizeof(int), s));
         stt->sdsn_fallbacks += 1;
         streamed = true;
@@ -963,6 +970,8 @@ void fram_default_options(fram_options* opt) {
   opt->many_workers = 16;
   opt->N0 = nullptr;
   opt->N_out = nullptr;
+  opt->onchip_roll_us = 0;
+  opt->onchip_barrier_us = 0;
 }
 
 fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
@@ -1175,12 +1184,8 @@ fram_status fram_sdsn_project_dev(fram_ctx* c, const float* dK, int ldk, int n, 
     if (r != FRAM_OK) return r;
     r = read_state(c, st, s);
     if (r != FRAM_OK) return r;
-    if (c->hst->invalid & fram::kInvalidBarrier) {
-      c->err = "on-chip SDSN barrier timed out";
-      return FRAM_EDEVICE;
-    }
-    if (c->hst->invalid & fram::kInvalidRollCall) {
-      // Nothing was done (the input is untouched): stream instead.
+    if (c->hst->invalid & (fram::kInvalidRollCall | fram::kInvalidBarrier)) {
+      // Nothing was written (the input is untouched): stream instead.
       HIPCHK(fram::launch_zero(&st->invalid, sizeof(int), s));
       stt.sdsn_fallbacks = 1;
       streamed = true;

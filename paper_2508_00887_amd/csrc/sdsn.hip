@@ -24,8 +24,9 @@
 // Tiles are BM x BM with 4*BM threads: each wave streams 16 rows of the tile,
 // each lane a float4 of columns, so every global access of a wave is one or
 // more contiguous 1 KB runs.  Row partials are summed in FP64 across the lanes
-// of a row with DPP lane exchanges; column partials stay in registers until
-// the end of the tile and are then summed in FP64 through LDS.
+// of a row by a transposing pairwise tree over all of the wave's rows at once
+// (lane swaps and DPP); column partials stay in registers until the end of the
+// tile and are then summed in FP64 through LDS.
 #include "fram_internal.h"
 #include "sdsn_common.h"
 
@@ -139,8 +140,10 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
                                  s_chain[0][3][tid]);
       const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
                                  s_chain[1][3][tid]);
-      s_a[tid] = (float)(half - sd * ri / dn);
-      s_b[tid] = (float)(half - sd * cj / dn);
+      // Rows and columns past n get -inf, so their entries (zero) map to
+      // max(0, -inf) = 0 without a test per entry.
+      s_a[tid] = (bm * BM + tid < n) ? (float)(half - sd * ri / dn) : -INFINITY;
+      s_b[tid] = (bn * BM + tid < n) ? (float)(half - sd * cj / dn) : -INFINITY;
     }
     __syncthreads();
   } else {
@@ -157,6 +160,7 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
   float4 bt = make_float4(0.f, 0.f, 0.f, 0.f);
   if (PASS) bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
   float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
+  RowSums<BM> rows;
   float lmax = -INFINITY;
   const bool c0 = j < n, c1 = j + 1 < n, c2 = j + 2 < n, c3 = j + 3 < n;
 
@@ -168,16 +172,15 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
 #pragma unroll
     for (int stp = 0; stp < STEPS; ++stp) {
       const int rl = w * 16 + stp * RPW + q;
-      const bool in = rl < n;
       const float ai = s_a[rl];
       const float4 x = xv[stp];
       float4 y;
-      y.x = (in && c0) ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
-      y.y = (in && c1) ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
-      y.z = (in && c2) ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
-      y.w = (in && c3) ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
+      y.x = fmaxf(0.0f, fmaf(s, x.x, ai + bt.x));
+      y.y = fmaxf(0.0f, fmaf(s, x.y, ai + bt.y));
+      y.z = fmaxf(0.0f, fmaf(s, x.z, ai + bt.z));
+      y.w = fmaxf(0.0f, fmaf(s, x.w, ai + bt.w));
       *reinterpret_cast<float4*>(a.dst + (size_t)rl * np + j) = y;
-      tile_step_sums<BM>(y, rl, s_rowsum, cacc);
+      tile_step_sums<BM>(y, stp, rows, cacc);
     }
   } else {
 #pragma unroll
@@ -193,10 +196,10 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
         float4* row = reinterpret_cast<float4*>(a.dst + (size_t)i * np + j);
         const float4 x = *row;
         const float ai = s_a[rl];
-        y.x = c0 ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
-        y.y = c1 ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
-        y.z = c2 ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
-        y.w = c3 ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
+        y.x = fmaxf(0.0f, fmaf(s, x.x, ai + bt.x));
+        y.y = fmaxf(0.0f, fmaf(s, x.y, ai + bt.y));
+        y.z = fmaxf(0.0f, fmaf(s, x.z, ai + bt.z));
+        y.w = fmaxf(0.0f, fmaf(s, x.w, ai + bt.w));
         *row = y;
       } else {
         const float* row = a.src + (size_t)i * a.ld_src + j;
@@ -214,9 +217,10 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
     } else if (!PASS && a.dst != nullptr && a.dst != a.src) {
       *reinterpret_cast<float4*>(a.dst + (size_t)i * np + j) = y;
     }
-    tile_step_sums<BM>(y, rl, s_rowsum, cacc);
+    tile_step_sums<BM>(y, stp, rows, cacc);
   }
   }
+  rows.finish(w, s_rowsum);
   tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.out.rowp, a.out.colp, a.out.tot, bm, bn,
                     nb, np);
   if (!PASS) {

@@ -7,13 +7,127 @@
 namespace fram {
 namespace {
 
-// Block reductions: a butterfly inside each wave, then every thread adds the
-// per-wave results in wave order.  The value is the same in every workgroup
-// for the same inputs (fixed order), which the pass loop relies on.
+// ---- Cross-lane moves (64-lane waves).
+
+// DPP move inside 16-lane rows, for one FP64 value; every source lane of the
+// controls used here is valid.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kDppXor1 = 0xB1;      // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppXor2 = 0x4E;      // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppXor8 = 0x128;     // row_ror:8 inside a 16-lane row: lane ^ 8
+constexpr int kDppHalfMirror = 0x141;  // lane 8k+i <-> lane 8k+7-i (pairs bit-2 halves)
+
+// Exchange between two registers by lane blocks (gfx950 permlane swaps).
+// swap32: a = [a_lo | b_lo], b = [a_hi | b_hi] by 32-lane halves.
+// swap16: a = [a0 b0 a2 b2], b = [a1 b1 a3 b3] by 16-lane rows.
+__device__ __forceinline__ void swap32_f64(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned long long na = ((unsigned long long)hi[0] << 32) | lo[0];
+  const unsigned long long nb = ((unsigned long long)hi[1] << 32) | lo[1];
+  a = __builtin_bit_cast(double, na);
+  b = __builtin_bit_cast(double, nb);
+}
+__device__ __forceinline__ void swap16_f64(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const unsigned long long na = ((unsigned long long)hi[0] << 32) | lo[0];
+  const unsigned long long nb = ((unsigned long long)hi[1] << 32) | lo[1];
+  a = __builtin_bit_cast(double, na);
+  b = __builtin_bit_cast(double, nb);
+}
+// (The vector elements are copied to scalars before the bit casts: this
+// compiler's __builtin_bit_cast of an element of an ext_vector_type reads
+// element 0 whatever the index.)
+__device__ __forceinline__ void swap32_f32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned r0 = r[0], r1 = r[1];
+  a = __builtin_bit_cast(float, r0);
+  b = __builtin_bit_cast(float, r1);
+}
+__device__ __forceinline__ void swap16_f32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  const unsigned r0 = r[0], r1 = r[1];
+  a = __builtin_bit_cast(float, r0);
+  b = __builtin_bit_cast(float, r1);
+}
+
+// One step of a transposing pairwise sum at lane bit B (5 ... 2): the lanes
+// whose bit B is 0 return a + (a of their partner lane), the others
+// b + (b of theirs); the partner differs in bit B only (in the half-row
+// mirror's pairing for B = 2).  Two values per lane become one, and no lane's
+// work is wasted.
+template <int B>
+__device__ __forceinline__ double pair_step(double a, double b) {
+  static_assert(B >= 2 && B <= 5, "lane bits 2-5");
+  if constexpr (B == 5) {
+    swap32_f64(a, b);
+    return a + b;
+  } else if constexpr (B == 4) {
+    swap16_f64(a, b);
+    return a + b;
+  } else {
+    const bool up = (threadIdx.x >> B) & 1;
+    const double send = up ? a : b;
+    const double keep = up ? b : a;
+    return keep + dpp_f64<B == 3 ? kDppXor8 : kDppHalfMirror>(send);
+  }
+}
+
+// Sum (max) over the 64 lanes of a wave in a fixed pairing order (bit 5, 4,
+// 3, the half-row mirror, bits 1 and 0); every lane receives the result.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  double t = v;
+  swap32_f64(v, t);
+  v = v + t;
+  t = v;
+  swap16_f64(v, t);
+  v = v + t;
+  v += dpp_f64<kDppXor8>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppXor1>(v);
+  return v;
+}
+__device__ __forceinline__ float wave_max_f32(float v) {
+  float t = v;
+  swap32_f32(v, t);
+  v = fmaxf(v, t);
+  t = v;
+  swap16_f32(v, t);
+  v = fmaxf(v, t);
+  v = fmaxf(v, dpp_f32<kDppXor8>(v));
+  v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
+  v = fmaxf(v, dpp_f32<kDppXor2>(v));
+  v = fmaxf(v, dpp_f32<kDppXor1>(v));
+  return v;
+}
+
+// Block reductions: the wave sums above, then every thread adds the per-wave
+// results in wave order.  The value is the same in every workgroup for the
+// same inputs (fixed order), which the pass loop relies on.
 template <int NT>
 __device__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_sum_f64(v);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = 0.0;
@@ -25,8 +139,7 @@ __device__ double block_sum(double v, double* sh) {
 
 template <int NT>
 __device__ float block_max(float v, float* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  v = wave_max_f32(v);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   float r = -INFINITY;
@@ -100,44 +213,6 @@ __device__ __forceinline__ const T& at_u32(const T* base, unsigned off) {
                                      (size_t)(off * (unsigned)sizeof(T)));
 }
 
-// Lane exchange inside a 16-lane DPP row, for one FP64 value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// FP64 sum over the LPR lanes (16, 32 or 64) that hold one tile row, in a
-// fixed order: a butterfly inside each 16-lane DPP row (neighbour, pair,
-// half-row mirror, row mirror), then the DPP rows of the group in increasing
-// order.  Every lane of the group receives the sum.  Must be reached by all
-// 64 lanes of the wave (lanes outside the matrix pass 0).
-template <int LPR>
-__device__ __forceinline__ double row_group_sum(double v) {
-  static_assert(LPR == 16 || LPR == 32 || LPR == 64, "row group of 16, 32 or 64 lanes");
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  if constexpr (LPR == 16) {
-    return v;
-  } else {
-    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
-    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
-    if constexpr (LPR == 64) return (r0 + r1) + (r2 + r3);
-    return (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
-  }
-}
-
 // Layout of a BM x BM tile over 4*BM threads: each wave holds 16 rows; a row
 // is LPR = BM/4 lanes with four consecutive columns each; a wave step covers
 // RPW = 64/LPR rows, so every thread visits STEPS = 16/RPW rows.
@@ -149,14 +224,60 @@ struct TileShape {
   static constexpr int STEPS = 16 / RPW;
 };
 
-// Per-row contribution of one tile step: the row's FP64 sum (lane partials
-// are FP32 sums of four entries) goes to s_rowsum[rl]; the column sums
-// accumulate in cacc (FP32, at most 16 rows per lane).
+// FP64 row sums of a wave's 16 tile rows, formed all at once.  Step stp of a
+// lane contributes the FP32 sum of its four entries of row
+// w*16 + stp*RPW + lane/LPR.  The sums over the LPR lanes of each row are
+// built as a pairwise tree whose level l joins steps differing in bit l at
+// lane bit TOP - l (pair_step): the two values of a lane become one, so the
+// STEPS values per lane shrink to one, level by level, as the steps arrive
+// (at most LEVELS values wait at any time).  The lane then holds step
+// s = sum_l bit(lane, TOP - l) << l of its row group, summed over the lanes
+// that differ in bits TOP ... 2; bits 1 and 0 are added last, so all four
+// lanes of a quad hold the row's sum.
 template <int BM>
-__device__ __forceinline__ void tile_step_sums(const float4& y, int rl, double* s_rowsum,
+struct RowSums {
+  using TS = TileShape<BM>;
+  static constexpr int LEVELS = TS::STEPS == 16 ? 4 : (TS::STEPS == 8 ? 3 : 2);
+  static constexpr int TOP = LEVELS + 1;  // lane bit of level 0: 5, 4 or 3
+  static_assert((1 << LEVELS) == TS::STEPS && (2 << TOP) == TS::LPR, "tile shape");
+  double pend[LEVELS];
+  double sum;
+
+  // Step stp (a compile-time constant once the step loop is unrolled).
+  __device__ __forceinline__ void push(int stp, const float4& y) {
+    carry<0>(stp, (double)((y.x + y.y) + (y.z + y.w)));
+  }
+  template <int L>
+  __device__ __forceinline__ void carry(int stp, double v) {
+    if constexpr (L == LEVELS) {
+      sum = v;
+    } else {
+      if (((stp >> L) & 1) == 0) {
+        pend[L] = v;
+        return;
+      }
+      carry<L + 1>(stp, pair_step<TOP - L>(pend[L], v));
+    }
+  }
+  // After the last step: s_rowsum[row] for the wave's 16 rows.
+  __device__ __forceinline__ void finish(int w, double* s_rowsum) const {
+    double v = sum;
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    const int lane = threadIdx.x & 63;
+    int s = 0;
+#pragma unroll
+    for (int l = 0; l < LEVELS; ++l) s |= ((lane >> (TOP - l)) & 1) << l;
+    if ((lane & 3) == 0) s_rowsum[w * 16 + s * TS::RPW + lane / TS::LPR] = v;
+  }
+};
+
+// One tile step's contribution to the sums: its row partials (RowSums) and
+// the lane's column sums cacc (FP32, at most 16 rows per lane).
+template <int BM>
+__device__ __forceinline__ void tile_step_sums(const float4& y, int stp, RowSums<BM>& rows,
                                                float4& cacc) {
-  const double rs = row_group_sum<TileShape<BM>::LPR>((double)((y.x + y.y) + (y.z + y.w)));
-  if ((threadIdx.x & (TileShape<BM>::LPR - 1)) == 0) s_rowsum[rl] = rs;
+  rows.push(stp, y);
   cacc.x += y.x;
   cacc.y += y.y;
   cacc.z += y.z;
@@ -197,8 +318,8 @@ __device__ __forceinline__ void tile_partials(const float4& cacc, const double* 
     double v = 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) v += (double)s_colred[p * 4 + u][c];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
     if (p == 0) st(&at_u32(colp, (unsigned)(bm * np + bn * BM + c)), v);
   }
   const double tt = block_sum<TS::NT>(rowsum, s_red);

@@ -23,26 +23,30 @@
 //
 // Co-residency.  A workgroup that waits at the barrier holds its compute
 // unit, so the launch makes progress only if all of its workgroups are
-// resident at once.  Three rules make a wait that can never end impossible:
+// resident at once (and stay scheduled).  Three rules make a wait that can
+// never end impossible, and a launch that cannot complete harmless:
 //  * roll call: every workgroup first checks in and waits, for a bounded time,
 //    until the whole grid has; if it has not, every workgroup leaves before
-//    touching any data (late ones see the abort flag and leave at once), the
-//    state records the fallback, and the caller runs the streaming passes,
-//    which read the untouched input;
-//  * every later wait is bounded too, and a timeout aborts the whole grid;
-//  * the host orders the launches of this kernel one after the other across
-//    every stream of the process (each waits for the previous one's
-//    completion), so two such grids never compete for compute units; other
-//    kernels only delay a roll call, since they never wait for each other.
+//    touching any data;
+//  * every later wait is bounded too; a timeout (for instance while the queue
+//    of the launch is preempted) aborts the whole grid.  Every workgroup takes
+//    the same decision at each wait (see wait_until), and X, D and N are
+//    written only after the last pass, so an aborted launch leaves them as
+//    they were.  Either way the state records why, and the caller runs the
+//    streaming passes on the untouched input;
+//  * the host admits a launch only while the grids that may still run and
+//    this one fit on the device together (a compute-unit budget across every
+//    stream of the process), so such grids never compete for compute units;
+//    other kernels only delay a roll call, since they never wait for these.
 //
 // Barrier.  Arrival is counted per group of workgroups (blockIdx mod 8: the
 // XCD the hardware dispatches it to), and the last arrival of a group bumps
 // one release counter that every workgroup polls, so each pass costs a few
 // atomics per group and one poll target instead of all-to-all flags
 // (measured on MI355X with 256 workgroups, barrier plus the partial-sum
-// exchange: 4.9 us per pass, against 9.2 us with one counter for all).  The counters live in a per-context block that
-// the host zeroes before each launch (stream-ordered), and only grow within
-// a launch.
+// exchange: 4.9 us per pass, against 9.2 us with one counter for all).  The
+// counters live in a per-context block that the host zeroes before each
+// launch (stream-ordered), and only grow within a launch.
 #include "fram_internal.h"
 #include "sdsn_common.h"
 
@@ -57,8 +61,7 @@ namespace {
 constexpr int kLine = 32;  // unsigned ints per line
 __device__ __forceinline__ unsigned* sync_group(unsigned* sy, int g) { return sy + g * kLine; }
 __device__ __forceinline__ unsigned* sync_release(unsigned* sy) { return sy + 8 * kLine; }
-__device__ __forceinline__ unsigned* sync_abort(unsigned* sy) { return sy + 9 * kLine; }
-__device__ __forceinline__ unsigned* sync_roll(unsigned* sy) { return sy + 10 * kLine; }
+__device__ __forceinline__ unsigned* sync_roll(unsigned* sy) { return sy + 9 * kLine; }
 
 __device__ __forceinline__ unsigned ld_agent(unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -81,23 +84,35 @@ __device__ __forceinline__ T ld_coherent(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 waits until *p >= target, the abort flag is set, or `limit`
-// wall-clock ticks pass (then it sets the abort flag itself).  The result is
-// the same in every thread of the workgroup.
-__device__ bool wait_until(unsigned* p, unsigned target, unsigned* abortf, long long limit,
-                           int* s_ok) {
+// The counters that waits poll (roll call, release) carry an abort bit.
+constexpr unsigned kAbortBit = 0x80000000u;
+
+// Thread 0 waits until the count in *p reaches `target` or the abort bit is
+// set.  If `limit` wall-clock ticks pass first, it sets the abort bit, with a
+// compare-and-swap that succeeds only while the count is still short of the
+// target: so every workgroup decides the same way (all pass, or all see the
+// abort; a count completed before the abort is never revoked).  The bit stays
+// set, so every later wait on *p fails too.  The result is the same in every
+// thread of the workgroup.
+__device__ bool wait_until(unsigned* p, unsigned target, long long limit, int* s_ok) {
   if (threadIdx.x == 0) {
     int ok = 1;
     const long long t0 = wall_clock64();
-    while (ld_agent(p) < target) {
-      if (ld_agent(abortf) != 0) {
+    while (true) {
+      const unsigned v = ld_agent(p);
+      if (v & kAbortBit) {
         ok = 0;
         break;
       }
+      if (v >= target) break;
       if (wall_clock64() - t0 > limit) {
-        __hip_atomic_store(abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+        unsigned expect = v;
+        if (__hip_atomic_compare_exchange_strong(p, &expect, v | kAbortBit, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        continue;  // the count moved meanwhile: look again
       }
       __builtin_amdgcn_s_sleep(1);
     }
@@ -127,7 +142,7 @@ __device__ bool grid_barrier(unsigned* sy, unsigned epoch, long long limit, int*
     if (old == epoch * gsize - 1u)
       __hip_atomic_fetch_add(sync_release(sy), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  return wait_until(sync_release(sy), epoch * (unsigned)groups, sync_abort(sy), limit, s_ok);
+  return wait_until(sync_release(sy), epoch * (unsigned)groups, limit, s_ok);
 }
 
 // Tile steps (float4 per lane) kept in VGPRs; the rest of the tile lives in
@@ -180,7 +195,7 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
   // ---- roll call: nothing is read or written before the whole grid is in
   if (tid == 0)
     __hip_atomic_fetch_add(sync_roll(a.sync), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!wait_until(sync_roll(a.sync), (unsigned)G, sync_abort(a.sync), a.roll_ticks, &s_ok)) {
+  if (!wait_until(sync_roll(a.sync), (unsigned)G, a.roll_ticks, &s_ok)) {
     if (tid == 0) atomicOr(&a.st->invalid, kInvalidRollCall);
     return;
   }
@@ -203,6 +218,7 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
   xv.l = s_tile;
   float lmax = -INFINITY;
   float4 cacc = make_float4(0.f, 0.f, 0.f, 0.f);
+  RowSums<BM> rows;
 #pragma unroll
   for (int stp = 0; stp < STEPS; ++stp) {
     const int rl = w * 16 + stp * RPW + q;
@@ -226,8 +242,9 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
       if (c3) lmax = fmaxf(lmax, v.w);
     }
     xv.set(stp, v);
-    tile_step_sums<BM>(v, rl, s_rowsum, cacc);
+    tile_step_sums<BM>(v, stp, rows, cacc);
   }
+  rows.finish(w, s_rowsum);
   tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, a.p[0].rowp, a.p[0].colp, a.p[0].tot, bm,
                     bn, nb, np, CoherentStore());
   {
@@ -298,8 +315,10 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
                                  s_chain[0][3][tid]);
       const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
                                  s_chain[1][3][tid]);
-      s_a[tid] = (float)(half - sd * ri / dn);
-      s_b[tid] = (float)(half - sd * cj / dn);
+      // Rows and columns past n get -inf, so their entries (zero) map to
+      // max(0, -inf) = 0 without a test per entry.
+      s_a[tid] = (bm * BM + tid < n) ? (float)(half - sd * ri / dn) : -INFINITY;
+      s_b[tid] = (bn * BM + tid < n) ? (float)(half - sd * cj / dn) : -INFINITY;
     }
     __syncthreads();
     const float4 bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
@@ -308,17 +327,16 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
     for (int stp = 0; stp < STEPS; ++stp) {
       const int rl = w * 16 + stp * RPW + q;
       const float ai = s_a[rl];
-      float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (bm * BM + rl < n) {
-        const float4 x = xv.get(stp);
-        y.x = c0 ? fmaxf(0.0f, fmaf(s, x.x, ai + bt.x)) : 0.0f;
-        y.y = c1 ? fmaxf(0.0f, fmaf(s, x.y, ai + bt.y)) : 0.0f;
-        y.z = c2 ? fmaxf(0.0f, fmaf(s, x.z, ai + bt.z)) : 0.0f;
-        y.w = c3 ? fmaxf(0.0f, fmaf(s, x.w, ai + bt.w)) : 0.0f;
-      }
+      const float4 x = xv.get(stp);
+      float4 y;
+      y.x = fmaxf(0.0f, fmaf(s, x.x, ai + bt.x));
+      y.y = fmaxf(0.0f, fmaf(s, x.y, ai + bt.y));
+      y.z = fmaxf(0.0f, fmaf(s, x.z, ai + bt.z));
+      y.w = fmaxf(0.0f, fmaf(s, x.w, ai + bt.w));
       xv.set(stp, y);
-      tile_step_sums<BM>(y, rl, s_rowsum, cacc);
+      tile_step_sums<BM>(y, stp, rows, cacc);
     }
+    rows.finish(w, s_rowsum);
     tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, out.rowp, out.colp, out.tot, bm, bn, nb,
                       np, CoherentStore());
   }

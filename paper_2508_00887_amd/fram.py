@@ -70,6 +70,8 @@ class Options(ctypes.Structure):
         ("many_workers", ctypes.c_int),
         ("N0", ctypes.c_void_p),
         ("N_out", ctypes.c_void_p),
+        ("onchip_roll_us", ctypes.c_int),
+        ("onchip_barrier_us", ctypes.c_int),
     ]
 
 
@@ -241,9 +243,12 @@ VARIANTS = {"fram": 0, "dspfp": 1}
 
 def _options(prec="fp32", alpha=0.95, gamma_tol=1e-6, sdsn_max=1000, tile=0,
              profile=False, sdsn_mode="auto", stable_iters=0, stall_iters=0,
-             stall_delta=1e-3, variant="fram", dsn_iters=30, many_workers=16) -> Options:
+             stall_delta=1e-3, variant="fram", dsn_iters=30, many_workers=16,
+             onchip_roll_us=0, onchip_barrier_us=0) -> Options:
     o = Options()
     o.many_workers = int(many_workers)
+    o.onchip_roll_us = int(onchip_roll_us)
+    o.onchip_barrier_us = int(onchip_barrier_us)
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.dsn_iters = int(dsn_iters)
     o.stable_iters = int(stable_iters)
@@ -342,13 +347,14 @@ class Context:
         return perm.astype(np.int64), obj.value, stats.as_dict()
 
     def sdsn_project(self, K, theta=2.0, gamma_tol=1e-6, sdsn_max=1000, tile=0,
-                     sdsn_mode="auto", profile=False):
+                     sdsn_mode="auto", profile=False, onchip_roll_us=0, onchip_barrier_us=0):
         """fram_sdsn_project_ex on a host matrix; returns (X, stats dict)."""
         K = _f32(K)
         n = K.shape[0]
         X = np.empty((n, n), dtype=np.float32)
         stats = Stats()
-        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile, profile, sdsn_mode)
+        o = _options("fp32", 0.95, gamma_tol, sdsn_max, tile, profile, sdsn_mode,
+                     onchip_roll_us=onchip_roll_us, onchip_barrier_us=onchip_barrier_us)
         st = self.lib.fram_sdsn_project_ex(self.handle, _ptr(K), n, theta, ctypes.byref(o),
                                            _ptr(X), ctypes.byref(stats))
         _check(self.handle, st, "fram_sdsn_project_ex")

@@ -83,7 +83,9 @@ def test_invalid_scalars_and_pointers(hctx):
                                          ("profile", 3), ("stall_iters", -1),
                                          ("stall_delta", 0.0), ("stall_delta", float("nan")),
                                          ("variant", 2), ("variant", -1), ("dsn_iters", 0),
-                                         ("many_workers", 0), ("many_workers", 33)])
+                                         ("many_workers", 0), ("many_workers", 33),
+                                         ("onchip_roll_us", -1), ("onchip_barrier_us", -5),
+                                         ("onchip_barrier_us", 60000001)])
 def test_invalid_options(hctx, field, value):
     o = F.fram_default_options()
     setattr(o, field, value)

@@ -126,6 +126,31 @@ def test_onchip_equals_streaming_bitwise(ctx, n):
     np.testing.assert_array_equal(Xs, Xo)
 
 
+@pytest.mark.parametrize("n", [300, 4000])
+def test_onchip_forced_fallbacks_equal_streaming(ctx, n):
+    # A 1 us bound on the pass barriers (the roll call keeps its default)
+    # makes the first barrier wait time out: the grid abandons the launch
+    # without writing, and the projection streams from the untouched input.
+    # A 1 us roll-call bound abandons it before any pass, or lets it run when
+    # every workgroup checked in within the bound.  Every outcome must give
+    # the streaming result bit for bit.
+    K = (np.random.default_rng(7 + n).random((n, n)) ** 2).astype(np.float32)
+    Xs, ss = ctx.sdsn_project(K, 2.0, sdsn_mode="stream")
+    Xb, sb = ctx.sdsn_project(K, 2.0, sdsn_mode="onchip", onchip_barrier_us=1)
+    Xr, sr = ctx.sdsn_project(K, 2.0, sdsn_mode="onchip", onchip_roll_us=1)
+    for X, st in [(Xb, sb), (Xr, sr)]:
+        assert st["sdsn_onchip"] + st["sdsn_fallbacks"] == 1
+        assert st["sdsn_passes"] == ss["sdsn_passes"] and st["gamma"] == ss["gamma"]
+        np.testing.assert_array_equal(X, Xs)
+    if n == 4000:
+        # 256 workgroups never all reach the first barrier within 1 us.
+        assert sb["sdsn_fallbacks"] == 1
+    # and a later projection on the same context runs on chip again
+    Xo, so = ctx.sdsn_project(K, 2.0, sdsn_mode="onchip")
+    assert so["sdsn_onchip"] == 1
+    np.testing.assert_array_equal(Xo, Xs)
+
+
 @pytest.mark.parametrize("mode", ["stream", "onchip"])
 def test_modes_match_oracle_theta10(ctx, mode):
     n = 500

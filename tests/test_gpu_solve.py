@@ -244,6 +244,24 @@ def test_onchip_and_streaming_solves_agree(ctx, n, prec):
     assert abs(s1["delta"] - s2["delta"]) <= 1e-12 * max(s1["delta"], 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_onchip_barrier_aborts_fall_back_inside_solves(ctx, prec):
+    # Every on-chip launch of the solve gives up at its first pass barrier
+    # (1 us bound); each iteration's projection and N update then stream from
+    # the same X, so the solve equals the streaming one bit for bit.
+    pr = synth.make_pair(4000, 0.3, 0.05, 5200)
+    N1 = np.empty((pr.n, pr.n), dtype=np.float32)
+    N2 = np.empty_like(N1)
+    p1, o1, s1 = ctx.solve(pr.A, pr.B, iters=4, prec=prec, sdsn_mode="stream", N_out=N1)
+    p2, o2, s2 = ctx.solve(pr.A, pr.B, iters=4, prec=prec, sdsn_mode="onchip",
+                           onchip_barrier_us=1, N_out=N2)
+    assert s2["outer_iters"] == 4 and s2["sdsn_fallbacks"] + s2["sdsn_onchip"] == 4
+    assert s2["sdsn_fallbacks"] >= 1
+    np.testing.assert_array_equal(N1, N2)
+    np.testing.assert_array_equal(p1, p2)
+    assert o1 == o2 and s1["sdsn_passes"] == s2["sdsn_passes"]
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_stability_stop_matches_oracle(ctx, seed):
     pr = next(synth.config_pairs(0, [seed]))
