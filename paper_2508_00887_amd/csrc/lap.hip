@@ -56,6 +56,29 @@ __global__ __launch_bounds__(NT) void lap_kernel(LapProblem one,
   if (threadIdx.x == 0 && p.paths_out != nullptr) *p.paths_out = r;
 }
 
+// One problem with its row reduction given, n <= 256 * C: the solver with
+// the column state in registers (lap_solve_reg), 256 threads.
+template <int C>
+__global__ __launch_bounds__(256) void lap_reg_kernel(LapProblem p) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ LapShared<4> sh;
+  const LapRegArrays a = lap_reg_carve(lds, p.n);
+  const double* vpart = reinterpret_cast<const double*>(p.ws + vpart_offset(p.n));
+  const int r = lap_solve_reg<256, C>(p.w, p.n, (size_t)p.ld, p.sigma, p.u_init, vpart,
+                                      col_chunks(p.n), a, sh);
+  if (threadIdx.x == 0 && p.paths_out != nullptr) *p.paths_out = r;
+}
+
+template <int C>
+hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
+  const size_t shm = lap_reg_lds_bytes(p.n);
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lap_reg_kernel<C>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  lap_reg_kernel<C><<<1, 256, shm, s>>>(p);
+  return hipGetLastError();
+}
+
 bool lap_in_lds(int max_n) { return lap_array_bytes(max_n) <= kLapLdsBytes; }
 
 }  // namespace
@@ -79,6 +102,13 @@ hipError_t launch_lap(const LapProblem* one, const LapProblem* probs, int count,
     colmin_kernel<<<grid, 256, 0, s>>>(p1.w, p1.n, p1.ld, p1.u_init,
                                        reinterpret_cast<double*>(p1.ws + vpart_offset(p1.n)),
                                        chunks);
+  }
+  // A single problem with its row reduction given and n <= 4096: the
+  // register-resident solver.
+  if (one != nullptr && p1.u_ready && p1.n > 0) {
+    if (p1.n <= 256 * 4) return launch_lap_reg<4>(p1, s);
+    if (p1.n <= 256 * 8) return launch_lap_reg<8>(p1, s);
+    if (p1.n <= 256 * 16) return launch_lap_reg<16>(p1, s);
   }
   const bool lds = lap_in_lds(max_n);
   const size_t shm = lds ? lap_array_bytes(max_n) : 0;

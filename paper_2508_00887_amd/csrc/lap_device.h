@@ -419,4 +419,305 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
   return fail ? -1 : unmatched;
 }
 
+// ---------------------------------------------------------------------------
+// The same solver with the column state in registers, for n <= NT * C and a
+// given row reduction (u_init, v_part).  Thread t owns the C consecutive
+// columns t*C ... t*C + C - 1 and keeps their prices v, tentative distances
+// and scanned flags in registers; the row duals u, the matching, the
+// predecessors and the unmatched-row list stay in LDS.  lap_solve spends most
+// of a Dijkstra step or bid on work that every one of its 16 waves repeats
+// (the wave reductions, the merge of the posted minima, LDS reads of the
+// column arrays); with one wave per SIMD and the columns in registers that
+// work is done once per SIMD.  The rules, the FP64 arithmetic of every
+// distance and potential, and the tie order (lowest column) are those of
+// lap_solve: the minimum and best-two of a row do not depend on how its
+// columns are split over threads, so both give the same assignment.
+struct LapRegArrays {
+  double* u;      // row duals
+  double* vinit;  // column prices at the start (read across threads once)
+  int* row_of;
+  int* col_of;
+  int* pred;
+  int* freel;
+};
+
+__host__ __device__ inline size_t lap_reg_lds_bytes(int n) {
+  return ((size_t)n * (2 * 8 + 4 * 4) + 15) / 16 * 16;
+}
+
+__device__ inline LapRegArrays lap_reg_carve(char* base, int n) {
+  LapRegArrays a;
+  a.u = reinterpret_cast<double*>(base);
+  a.vinit = a.u + n;
+  a.row_of = reinterpret_cast<int*>(a.vinit + n);
+  a.col_of = a.row_of + n;
+  a.pred = a.col_of + n;
+  a.freel = a.pred + n;
+  return a;
+}
+
+// Row i's entries in this thread's columns (0 past n); float4 loads where the
+// row is 16-byte aligned and the thread's columns all lie inside it.
+template <int C>
+__device__ __forceinline__ void lap_row_cols(const float* __restrict__ row, int j0, int n, bool vec,
+                                             float (&x)[C]) {
+  if (vec && j0 + C <= n) {
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q) {
+      const float4 t = *reinterpret_cast<const float4*>(row + j0 + 4 * q);
+      x[4 * q] = t.x;
+      x[4 * q + 1] = t.y;
+      x[4 * q + 2] = t.z;
+      x[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = (j0 + c < n) ? row[j0 + c] : 0.0f;
+  }
+}
+
+template <int NT, int C>
+__device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int32_t* sigma,
+                             const double* __restrict__ u_init, const double* v_part,
+                             int v_chunks, LapRegArrays a, LapShared<NT / 64>& sh) {
+  static_assert(C % 4 == 0 && C <= 32, "columns per thread");
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const double inf = __builtin_inf();
+  const int j0 = tid * C;
+  const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
+
+  // ---- duals: u_i = -max_j W_ij (given), v_j = min of the partial column
+  // minima (or 0)
+  for (int i = tid; i < n; i += NT) a.u[i] = u_init[i];
+  double v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = j0 + c;
+    double vj = 0.0;
+    if (j < n) {
+      if (v_part != nullptr) {
+        vj = v_part[j];
+        for (int k = 1; k < v_chunks; ++k) vj = fmin(vj, v_part[(size_t)k * n + j]);
+      }
+      a.vinit[j] = vj;
+      a.row_of[j] = INT_MAX;
+    }
+    v[c] = vj;
+  }
+  __syncthreads();
+  // ---- keep tight argmax columns; a column goes to its lowest claiming row
+  for (int i = tid; i < n; i += NT) {
+    const int j = sigma[i];
+    if (j >= 0 && j < n && (-(double)W[(size_t)i * ld + j]) - a.u[i] - a.vinit[j] == 0.0)
+      atomicMin(&a.row_of[j], i);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    const int j = sigma[i];
+    a.col_of[i] = (j >= 0 && j < n && a.row_of[j] == i) ? j : -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    if (j0 + c < n && a.row_of[j0 + c] == INT_MAX) a.row_of[j0 + c] = -1;
+
+  // ---- unmatched rows in increasing order (ordered compaction)
+  int nfree = 0;
+  for (int base = 0; base < n; base += NT) {
+    const int i = base + tid;
+    const bool f = i < n && a.col_of[i] == -1;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) sh.cnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = nfree;
+    for (int w = 0; w < wave; ++w) off += sh.cnt[w];
+    if (f) a.freel[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    for (int w = 0; w < NW; ++w) nfree += sh.cnt[w];
+    __syncthreads();
+  }
+  const int unmatched = nfree;
+
+  // ---- augmenting row reduction (bids), as in lap_solve
+  float x[C];
+  {
+    int budget = 4 * nfree + n / 2;
+    for (int pass = 0; pass < 2 && nfree > 0 && budget > 0; ++pass) {
+      int k = 0, nnext = 0;
+      const int cnt = nfree;
+      while (k < cnt) {
+        if (budget <= 0) {
+          if (tid == 0)
+            for (int t = k; t < cnt; ++t) a.freel[nnext + (t - k)] = a.freel[t];
+          nnext += cnt - k;
+          __syncthreads();
+          break;
+        }
+        --budget;
+        const int i = a.freel[k++];
+        lap_row_cols<C>(W + (size_t)i * ld, j0, n, vec, x);
+        double m1 = inf, m2 = inf;
+        int j1 = INT_MAX, j2 = INT_MAX;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          // Columns past n take part as (inf, INT_MAX), which never ranks
+          // above "no choice", so they can never be bid for.
+          const int j = (j0 + c < n) ? j0 + c : INT_MAX;
+          const double h = (j != INT_MAX) ? -(double)x[c] - v[c] : inf;
+          const bool b1 = lap_lex_less(h, j, m1, j1), b2 = lap_lex_less(h, j, m2, j2);
+          m2 = b1 ? m1 : (b2 ? h : m2);
+          j2 = b1 ? j1 : (b2 ? j : j2);
+          m1 = b1 ? h : m1;
+          j1 = b1 ? j : j1;
+        }
+        lap_wave_top2(m1, j1, m2, j2);
+        if (lane == 0) {
+          sh.b1[wave] = m1;
+          sh.b2[wave] = m2;
+          sh.c1[wave] = j1;
+          sh.c2[wave] = j2;
+        }
+        __syncthreads();
+        m1 = sh.b1[0];
+        m2 = sh.b2[0];
+        j1 = sh.c1[0];
+        j2 = sh.c2[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+          lap_top2_merge(m1, j1, m2, j2, sh.b1[w], sh.c1[w], sh.b2[w], sh.c2[w]);
+        if (j2 == INT_MAX) {  // fewer than two finite choices: left to the paths
+          if (tid == 0) a.freel[nnext] = i;
+          ++nnext;
+          __syncthreads();
+          continue;
+        }
+        int i0 = a.row_of[j1];
+        const bool lower = m1 < m2;
+        if (lower) {
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (j0 + c == j1) v[c] -= m2 - m1;
+        } else if (i0 >= 0) {
+          j1 = j2;
+          i0 = a.row_of[j2];
+        }
+        __syncthreads();  // every thread has read row_of before it changes
+        if (tid == 0) {
+          if (i0 >= 0) a.col_of[i0] = -1;
+          a.row_of[j1] = i;
+          a.col_of[i] = j1;
+          a.u[i] = m2;
+        }
+        if (i0 >= 0) {
+          if (lower) {
+            --k;
+            if (tid == 0) a.freel[k] = i0;
+          } else {
+            if (tid == 0) a.freel[nnext] = i0;
+            ++nnext;
+          }
+        }
+        __syncthreads();
+      }
+      nfree = nnext;
+    }
+  }
+
+  // ---- one shortest augmenting path per row still unmatched
+  int fail = 0;
+  int par = 0;
+  for (int k = 0; k < nfree; ++k) {
+    const int i0 = a.freel[k];
+    const double ui0 = a.u[i0];
+    lap_row_cols<C>(W + (size_t)i0 * ld, j0, n, vec, x);
+    double dist[C];
+    unsigned scanned = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = j0 + c;
+      if (j < n) {
+        dist[c] = (-(double)x[c] - ui0) - v[c];
+        a.pred[j] = i0;
+      } else {
+        dist[c] = inf;
+        scanned |= 1u << c;
+      }
+    }
+    int jend = -1;
+    double D = 0.0;
+    while (true) {
+      double bd = inf;
+      int bj = INT_MAX;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (!((scanned >> c) & 1u) && dist[c] < bd) {
+          bd = dist[c];
+          bj = j0 + c;
+        }
+      lap_wave_min(bd, bj);
+      if (lane == 0) {
+        sh.wd[par][wave] = bd;
+        sh.wj[par][wave] = bj;
+      }
+      __syncthreads();
+      bd = sh.wd[par][0];
+      bj = sh.wj[par][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) lap_better(bd, bj, sh.wd[par][w], sh.wj[par][w]);
+      par ^= 1;
+      if (bj == INT_MAX) {  // no finite distance left
+        fail = 1;
+        break;
+      }
+      if (bj >= j0 && bj < j0 + C) scanned |= 1u << (bj - j0);
+      const int i = a.row_of[bj];
+      if (i == -1) {
+        jend = bj;
+        D = bd;
+        break;
+      }
+      // Relax the unscanned columns through row i (matched to column bj).
+      const double ui = a.u[i];
+      lap_row_cols<C>(W + (size_t)i * ld, j0, n, vec, x);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if ((scanned >> c) & 1u) continue;
+        const double nd = ((bd + (-(double)x[c])) - ui) - v[c];
+        if (nd < dist[c]) {
+          dist[c] = nd;
+          a.pred[j0 + c] = i;
+        }
+      }
+    }
+    if (fail) break;
+    // Potentials, as in lap_solve.
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = j0 + c;
+      if (!((scanned >> c) & 1u) || j >= n || j == jend) continue;
+      v[c] += dist[c] - D;
+      a.u[a.row_of[j]] += D - dist[c];
+    }
+    if (tid == 0) a.u[i0] += D;
+    __syncthreads();
+    if (tid == 0) {  // flip the path
+      int j = jend;
+      while (true) {
+        const int i = a.pred[j];
+        const int jprev = a.col_of[i];
+        a.row_of[j] = i;
+        a.col_of[i] = j;
+        if (i == i0) break;
+        j = jprev;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NT) sigma[i] = fail ? -1 : a.col_of[i];
+  __syncthreads();
+  return fail ? -1 : unmatched;
+}
+
 }  // namespace fram
