@@ -327,10 +327,13 @@ fram_status fram_solve_attr_dev(fram_ctx* ctx, const double* dA, const double* d
  * the paper does with the Hungarian method (Sec. 6): perm_out maximises
  * sum_i W[i, perm_out[i]], i.e. it is the permutation P minimising ||P - W||_F.
  * Runs on the device in three phases: row maxima as the starting duals and
- * column minima of the reduced costs as the starting prices; two passes of
- * Jonker-Volgenant augmenting row reduction (bids of the free rows, at most
- * 4 * free + n / 2 of them); then one shortest augmenting path (with row and
- * column potentials) per row still free.  When the row argmax is already a
+ * column minima of the reduced costs as the starting prices; bids of the free
+ * rows (Jonker-Volgenant augmenting row reduction: for n < 1024 two
+ * sequential passes, at most 4 * free + n / 2 bids; from n = 1024 parallel
+ * rounds in which every free row bids at once and each column goes to its
+ * largest bid, until no row is left or 8 rounds bring no progress); then one
+ * shortest augmenting path (with row and column potentials) per row still
+ * free.  When the row argmax is already a
  * permutation it is returned as is.  Ties go to the lowest column.  The
  * solvers use the same device code for their final step.
  *   W        host, n*n floats, row-major, finite (else FRAM_EINVAL).

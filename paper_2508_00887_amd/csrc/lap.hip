@@ -18,6 +18,116 @@ __host__ __device__ inline size_t vpart_offset(int n) {
 
 __host__ __device__ inline int col_chunks(int n) { return n < kColChunks ? n : kColChunks; }
 
+// The state of the parallel bidding rounds (LapBidState), after the partial
+// column minima.
+__host__ __device__ inline size_t bid_offset(int n) {
+  return (vpart_offset(n) + (size_t)col_chunks(n) * n * 8 + 255) / 256 * 256;
+}
+__host__ __device__ inline size_t bid_bytes(int n) {
+  return ((size_t)n * (8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 8 + 8) + 64 + 255) / 256 * 256;
+}
+__host__ __device__ inline LapBidState bid_carve(char* ws, int n) {
+  char* b = ws + bid_offset(n);
+  LapBidState s;
+  s.u = reinterpret_cast<double*>(b);
+  s.v = s.u + n;
+  s.newu = s.v + n;
+  s.drop = s.newu + n;
+  s.key = reinterpret_cast<unsigned long long*>(s.drop + n);
+  s.row_of = reinterpret_cast<int*>(s.key + n);
+  s.col_of = s.row_of + n;
+  s.list[0] = s.col_of + n;
+  s.list[1] = s.list[0] + n;
+  s.tgt = s.list[1] + n;
+  s.ctl = s.tgt + n;
+  return s;
+}
+
+// Smallest n for which the assignment bids in parallel rounds first.
+constexpr int kBidMinN = 1024;
+// Rounds launched (the kernels of the rounds after the stop return at once).
+constexpr int kBidRounds = 64;
+
+// Start of the bidding rounds: u = -row maxima (given), v = the column
+// minima, the tight argmax pairs matched (a column to its lowest claiming
+// row), the other rows listed.  Three launches, as each step reads what the
+// previous one wrote across the grid.
+__global__ __launch_bounds__(256) void bid_init_kernel(LapBidState s, int n,
+                                                       const double* __restrict__ u_init,
+                                                       const double* __restrict__ vpart,
+                                                       int chunks) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t == 0) {
+    s.ctl[0] = s.ctl[1] = s.ctl[2] = s.ctl[4] = s.ctl[6] = 0;
+    s.ctl[3] = n + 1;
+  }
+  if (t >= n) return;
+  double vj = vpart[t];
+  for (int c = 1; c < chunks; ++c) vj = fmin(vj, vpart[(size_t)c * n + t]);
+  s.v[t] = vj;
+  s.u[t] = u_init[t];
+  s.row_of[t] = INT_MAX;
+  s.key[t] = 0;
+  s.tgt[t] = -1;
+}
+
+__global__ __launch_bounds__(256) void bid_match_kernel(LapBidState s, const float* __restrict__ W,
+                                                        int n, int ld,
+                                                        const int32_t* __restrict__ sigma) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = sigma[i];
+  if (j >= 0 && j < n && (-(double)W[(size_t)i * ld + j]) - s.u[i] - s.v[j] == 0.0)
+    atomicMin(&s.row_of[j], i);
+}
+
+__global__ __launch_bounds__(256) void bid_list_kernel(LapBidState s, int n,
+                                                       const int32_t* __restrict__ sigma) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int j = sigma[t];
+  const bool matched = j >= 0 && j < n && s.row_of[j] == t;
+  s.col_of[t] = matched ? j : -1;
+  if (!matched) {
+    s.list[0][atomicAdd(&s.ctl[0], 1)] = t;
+    atomicAdd(&s.ctl[6], 1);  // rows the row maxima left free (reported)
+  }
+  // A column nobody kept: unmatched.  (Reading a row_of that another thread
+  // turns from INT_MAX to -1 gives "not this row" either way.)
+  if (s.row_of[t] == INT_MAX) s.row_of[t] = -1;
+}
+
+// Round r (list p = r & 1): one wave per listed row.
+__global__ __launch_bounds__(256) void bid_round_kernel(LapBidState s, const float* __restrict__ W,
+                                                        int n, int ld, int p) {
+  if (s.ctl[2] != 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.ctl[p ^ 1] = 0;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= s.ctl[p]) return;
+  lap_bid_row(W, n, (size_t)ld, s, s.list[p][w]);
+}
+
+__global__ __launch_bounds__(256) void bid_resolve_kernel(LapBidState s, int p) {
+  if (s.ctl[2] != 0) return;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= s.ctl[p]) return;
+  lap_resolve_row(s, s.list[p][t], p ^ 1);
+}
+
+// After round r: stop once no row is left or the count has not fallen for
+// kBidStall rounds.
+__global__ void bid_control_kernel(LapBidState s, int q) {
+  if (threadIdx.x != 0 || s.ctl[2] != 0) return;
+  const int c = s.ctl[q];
+  if (c < s.ctl[3]) {
+    s.ctl[3] = c;
+    s.ctl[4] = 0;
+  } else {
+    s.ctl[4] += 1;
+  }
+  if (c == 0 || s.ctl[4] >= kBidStall) s.ctl[2] = 1;
+}
+
 // Partial column minima of the reduced costs after the row reduction:
 // part[c * n + j] = min over the rows i of chunk c of (-(double)w_ij - u_i),
 // finite values only (a column with none gets 0, i.e. no reduction).
@@ -59,23 +169,41 @@ __global__ __launch_bounds__(NT) void lap_kernel(LapProblem one,
 // One problem with its row reduction given, n <= 256 * C: the solver with
 // the column state in registers (lap_solve_reg), 256 threads.
 template <int C>
-__global__ __launch_bounds__(256) void lap_reg_kernel(LapProblem p) {
+__global__ __launch_bounds__(256) void lap_reg_kernel(LapProblem p, int after_bids) {
   extern __shared__ __align__(16) char lds[];
   __shared__ LapShared<4> sh;
   const LapRegArrays a = lap_reg_carve(lds, p.n);
   const double* vpart = reinterpret_cast<const double*>(p.ws + vpart_offset(p.n));
+  const LapBidState bs = bid_carve(p.ws, p.n);
   const int r = lap_solve_reg<256, C>(p.w, p.n, (size_t)p.ld, p.sigma, p.u_init, vpart,
-                                      col_chunks(p.n), a, sh);
+                                      col_chunks(p.n), a, sh, after_bids ? &bs : nullptr);
   if (threadIdx.x == 0 && p.paths_out != nullptr) *p.paths_out = r;
 }
 
 template <int C>
 hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
-  const size_t shm = lap_reg_lds_bytes(p.n);
+  const int n = p.n;
+  const bool bids = n >= kBidMinN;
+  if (bids) {
+    // The bidding rounds on the whole device, then the paths in one workgroup.
+    const LapBidState bs = bid_carve(p.ws, n);
+    const double* vpart = reinterpret_cast<const double*>(p.ws + vpart_offset(n));
+    const int blocks = (n + 255) / 256;
+    bid_init_kernel<<<blocks, 256, 0, s>>>(bs, n, p.u_init, vpart, col_chunks(n));
+    bid_match_kernel<<<blocks, 256, 0, s>>>(bs, p.w, n, p.ld, p.sigma);
+    bid_list_kernel<<<blocks, 256, 0, s>>>(bs, n, p.sigma);
+    for (int r = 0; r < kBidRounds; ++r) {
+      const int q = r & 1;
+      bid_round_kernel<<<(n + 3) / 4, 256, 0, s>>>(bs, p.w, n, p.ld, q);
+      bid_resolve_kernel<<<blocks, 256, 0, s>>>(bs, q);
+      bid_control_kernel<<<1, 64, 0, s>>>(bs, q ^ 1);
+    }
+  }
+  const size_t shm = lap_reg_lds_bytes(n);
   const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lap_reg_kernel<C>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  lap_reg_kernel<C><<<1, 256, shm, s>>>(p);
+  lap_reg_kernel<C><<<1, 256, shm, s>>>(p, bids ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -84,7 +212,7 @@ bool lap_in_lds(int max_n) { return lap_array_bytes(max_n) <= kLapLdsBytes; }
 }  // namespace
 
 size_t lap_workspace_bytes(int n) {
-  return (vpart_offset(n) + (size_t)col_chunks(n) * n * 8 + 255) / 256 * 256;
+  return bid_offset(n) + bid_bytes(n);
 }
 
 hipError_t launch_lap(const LapProblem* one, const LapProblem* probs, int count, int max_n,

@@ -420,6 +420,97 @@ __device__ int lap_solve(const float* __restrict__ W, int n, size_t ld, int32_t*
 }
 
 // ---------------------------------------------------------------------------
+// Parallel bidding: a Jacobi form of the augmenting row reduction above.  In
+// one round every unmatched row bids at once against the same column prices:
+// it finds its best and second-best reduced costs m1 <= m2 (columns j1, j2)
+// and asks for j1 with the price drop m2 - m1, or, when m1 == m2 and j1 is
+// taken, for j2 without a drop -- the choice a sequential bid makes.  Each
+// column goes to its largest bid (ties: the lowest row); the winner takes it
+// with u_i = m2, the column's price falls by the winner's drop, and the
+// displaced owner becomes unmatched.  Prices only fall and every winner's
+// column falls by its own drop alone, so the invariants of the sequential
+// version hold (every reduced cost >= 0, matched pairs tight); the rows left
+// unmatched when the rounds stop (none left, or no progress for a few rounds)
+// go to the shortest augmenting paths, which make the result exact.  Which
+// rows bid in a round is a set, and a column's winner depends only on the
+// bids, so the outcome does not depend on the order of the lists.
+struct LapBidState {
+  double* u;
+  double* v;
+  int* row_of;
+  int* col_of;
+  int* list[2];             // unmatched rows of the current / next round
+  unsigned long long* key;  // per column: the round's best bid (0: none)
+  int* tgt;                 // per row: the column it bid for (-1: no bid)
+  double* newu;             // per row: its u if it wins (m2)
+  double* drop;             // per row: its column's price drop if it wins
+  int* ctl;                 // [0..1] list counts, [2] stop, [3] best count, [4] stalled
+                            // rounds, [6] rows the row maxima left free
+};
+
+// Rounds without a smaller unmatched count after which bidding stops.
+constexpr int kBidStall = 8;
+
+
+__device__ __forceinline__ unsigned long long lap_bid_key(double d, int i) {
+  // Larger drops first, then lower rows; d >= 0 (or +inf), so the FP32 bit
+  // pattern orders like the value.
+  const float f = (float)d;
+  return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+}
+
+// One wave per unmatched row of list `p`: the row's bid.
+__device__ inline void lap_bid_row(const float* __restrict__ W, int n, size_t ld,
+                                   const LapBidState& s, int i) {
+  const int lane = threadIdx.x & 63;
+  const double inf = __builtin_inf();
+  const float* ri = W + (size_t)i * ld;
+  double m1 = inf, m2 = inf;
+  int j1 = INT_MAX, j2 = INT_MAX;
+  for (int j = lane; j < n; j += 64) {
+    const double h = -(double)ri[j] - s.v[j];
+    const bool b1 = lap_lex_less(h, j, m1, j1), b2 = lap_lex_less(h, j, m2, j2);
+    m2 = b1 ? m1 : (b2 ? h : m2);
+    j2 = b1 ? j1 : (b2 ? j : j2);
+    m1 = b1 ? h : m1;
+    j1 = b1 ? j : j1;
+  }
+  lap_wave_top2(m1, j1, m2, j2);
+  if (lane == 0) {
+    if (j2 == INT_MAX) {  // fewer than two finite choices: left to the paths
+      s.tgt[i] = -1;
+      return;
+    }
+    const bool lower = m1 < m2;
+    int target = j1;
+    if (!lower && s.row_of[j1] >= 0) target = j2;
+    const double d = lower ? m2 - m1 : 0.0;
+    s.tgt[i] = target;
+    s.newu[i] = m2;
+    s.drop[i] = d;
+    atomicMax(&s.key[target], lap_bid_key(d, i));
+  }
+}
+
+// After the bids of a round: row i of list p takes its column if its bid won
+// (and resets the column's key for the next round), else stays unmatched.
+__device__ inline void lap_resolve_row(const LapBidState& s, int i, int q) {
+  const int j = s.tgt[i];
+  int again = i;
+  if (j >= 0 && s.key[j] == lap_bid_key(s.drop[i], i)) {
+    const int i0 = s.row_of[j];
+    s.v[j] -= s.drop[i];
+    s.row_of[j] = i;
+    s.col_of[i] = j;
+    s.u[i] = s.newu[i];
+    s.key[j] = 0;
+    again = i0;
+    if (i0 >= 0) s.col_of[i0] = -1;
+  }
+  if (again >= 0) s.list[q][atomicAdd(&s.ctl[q], 1)] = again;
+}
+
+// ---------------------------------------------------------------------------
 // The same solver with the column state in registers, for n <= NT * C and a
 // given row reduction (u_init, v_part).  Thread t owns the C consecutive
 // columns t*C ... t*C + C - 1 and keeps their prices v, tentative distances
@@ -479,7 +570,8 @@ __device__ __forceinline__ void lap_row_cols(const float* __restrict__ row, int 
 template <int NT, int C>
 __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int32_t* sigma,
                              const double* __restrict__ u_init, const double* v_part,
-                             int v_chunks, LapRegArrays a, LapShared<NT / 64>& sh) {
+                             int v_chunks, LapRegArrays a, LapShared<NT / 64>& sh,
+                             const LapBidState* given = nullptr) {
   static_assert(C % 4 == 0 && C <= 32, "columns per thread");
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x;
@@ -489,10 +581,21 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
   const int j0 = tid * C;
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
 
+  double v[C];
+  if (given != nullptr) {
+    // The state left by the parallel bidding rounds: duals and matching.
+    for (int i = tid; i < n; i += NT) {
+      a.u[i] = given->u[i];
+      a.row_of[i] = given->row_of[i];
+      a.col_of[i] = given->col_of[i];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = (j0 + c < n) ? given->v[j0 + c] : 0.0;
+    __syncthreads();
+  } else {
   // ---- duals: u_i = -max_j W_ij (given), v_j = min of the partial column
   // minima (or 0)
   for (int i = tid; i < n; i += NT) a.u[i] = u_init[i];
-  double v[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int j = j0 + c;
@@ -523,6 +626,18 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
 #pragma unroll
   for (int c = 0; c < C; ++c)
     if (j0 + c < n && a.row_of[j0 + c] == INT_MAX) a.row_of[j0 + c] = -1;
+  }
+
+  // Columns of this thread still unmatched (bit c: column j0 + c).  Among
+  // columns at the same tentative distance the path search takes an
+  // unmatched one first: any column of least distance may end a shortest
+  // path, and on tie-heavy matrices (a constant N, as after one outer
+  // iteration) this ends each search at once instead of after scanning every
+  // matched column of that distance.
+  unsigned freecols = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    if (j0 + c < n && a.row_of[j0 + c] == -1) freecols |= 1u << c;
 
   // ---- unmatched rows in increasing order (ordered compaction)
   int nfree = 0;
@@ -538,12 +653,13 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
     for (int w = 0; w < NW; ++w) nfree += sh.cnt[w];
     __syncthreads();
   }
-  const int unmatched = nfree;
+  const int unmatched = given != nullptr ? given->ctl[6] : nfree;
 
-  // ---- augmenting row reduction (bids), as in lap_solve
+  // ---- augmenting row reduction (bids), as in lap_solve; none after the
+  // parallel rounds
   float x[C];
   {
-    int budget = 4 * nfree + n / 2;
+    int budget = given != nullptr ? 0 : 4 * nfree + n / 2;
     for (int pass = 0; pass < 2 && nfree > 0 && budget > 0; ++pass) {
       int k = 0, nnext = 0;
       const int cnt = nfree;
@@ -610,6 +726,7 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
           a.col_of[i] = j1;
           a.u[i] = m2;
         }
+        if (j1 >= j0 && j1 < j0 + C) freecols &= ~(1u << (j1 - j0));
         if (i0 >= 0) {
           if (lower) {
             --k;
@@ -648,14 +765,18 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
     int jend = -1;
     double D = 0.0;
     while (true) {
+      // Order: distance, then unmatched before matched, then column (key
+      // j for an unmatched column, n + j for a matched one).
       double bd = inf;
       int bj = INT_MAX;
 #pragma unroll
-      for (int c = 0; c < C; ++c)
-        if (!((scanned >> c) & 1u) && dist[c] < bd) {
+      for (int c = 0; c < C; ++c) {
+        const int key = ((freecols >> c) & 1u) ? j0 + c : n + j0 + c;
+        if (!((scanned >> c) & 1u) && (dist[c] < bd || (dist[c] == bd && key < bj))) {
           bd = dist[c];
-          bj = j0 + c;
+          bj = key;
         }
+      }
       lap_wave_min(bd, bj);
       if (lane == 0) {
         sh.wd[par][wave] = bd;
@@ -671,6 +792,7 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
         fail = 1;
         break;
       }
+      if (bj >= n) bj -= n;
       if (bj >= j0 && bj < j0 + C) scanned |= 1u << (bj - j0);
       const int i = a.row_of[bj];
       if (i == -1) {
@@ -701,6 +823,7 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
       a.u[a.row_of[j]] += D - dist[c];
     }
     if (tid == 0) a.u[i0] += D;
+    if (jend >= j0 && jend < j0 + C) freecols &= ~(1u << (jend - j0));
     __syncthreads();
     if (tid == 0) {  // flip the path
       int j = jend;

@@ -65,7 +65,9 @@ def test_assign_random_matches_oracle(ctx, n):
     assert value(W, p) == value(W, ref)
 
 
-# 4000 keeps the assignment's arrays in LDS; 4500, 6000 and 10000 use the workspace.
+# n <= 4096 runs the register solver (64 and 777 with sequential bids, 2048 and 4000
+# after parallel bidding rounds); 4500 keeps the arrays of the other solver in LDS,
+# 6000 and 10000 in the workspace.
 @pytest.mark.parametrize("n", [64, 777, 2048, 4000, 4500, 6000, 10000])
 def test_assign_near_permutation_matches_oracle(ctx, n):
     W = near_permutation(n, seed=n, collide_frac=0.05)
@@ -85,7 +87,7 @@ def test_assign_argmax_permutation_needs_no_path(ctx):
     assert ctx.last_stats()["lap_paths"] == 0
 
 
-@pytest.mark.parametrize("n,levels", [(60, 3), (257, 2), (1000, 5)])
+@pytest.mark.parametrize("n,levels", [(60, 3), (257, 2), (1000, 5), (1100, 4)])
 def test_assign_with_ties_is_optimal(ctx, n, levels):
     rng = np.random.default_rng(n + levels)
     W = rng.integers(0, levels, size=(n, n)).astype(np.float32)
@@ -105,6 +107,17 @@ def test_assign_constant_matrix_is_a_permutation(ctx):
     np.testing.assert_array_equal(ctx.assign(W), p)
 
 
+def test_assign_constant_matrix_with_parallel_bids(ctx):
+    # n >= 1024: the parallel rounds cannot place any row (every drop is 0 and
+    # every column is wanted by all), stop on the stall rule, and the paths
+    # finish the job.
+    W = np.full((1030, 1030), 0.5, dtype=np.float32)
+    p = ctx.assign(W)
+    check_perm(p, 1030)
+    assert ctx.last_stats()["lap_paths"] == 1029
+    np.testing.assert_array_equal(ctx.assign(W), p)
+
+
 def test_assign_dev_wide_leading_dimension_and_stream(ctx):
     import torch
     n, ld = 1500, 1536
@@ -119,10 +132,10 @@ def test_assign_dev_wide_leading_dimension_and_stream(ctx):
     np.testing.assert_array_equal(p, O.discretize(W.astype(np.float64)))
 
 
-def test_assign_dev_non_finite_row_is_reported(ctx):
+@pytest.mark.parametrize("n", [40, 1100])
+def test_assign_dev_non_finite_row_is_reported(ctx, n):
     import torch
     from paper_2508_00887_amd import fram as F
-    n = 40
     W = torch.rand((n, n), dtype=torch.float32, device="cuda")
     W[5, :] = float("nan")
     dp = torch.zeros(n, dtype=torch.int32, device="cuda")
