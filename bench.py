@@ -209,6 +209,7 @@ def batched_leg(Context, reps=2, cpu_pairs=16):
         "mean_accuracy": float(np.mean([np.mean(p == q.perm) for p, q in zip(perms, pairs)])),
         "mean_outer_iters": float(np.mean([s["outer_iters"] for s in stats])),
         "assignments_with_paths": int(sum(1 for s in stats if s["lap_paths"] > 0)),
+        "lockstep_pairs": int(sum(1 for q in pairs if 2 <= q.n <= 256)),
         "onchip_projections": int(sum(s["sdsn_onchip"] for s in stats)),
         "onchip_fallbacks": int(sum(s["sdsn_fallbacks"] for s in stats)),
         "gemm_precision": "bf16",

@@ -353,9 +353,19 @@ fram_status fram_assign_dev(fram_ctx* ctx, const float* dW, int ldw, int n, int3
  *   perm_out[i]  host, n[i] int32 (written); objective_out host, count doubles.
  *   opt          NULL = defaults; opt->N0 / opt->N_out must be NULL.
  *   stats        NULL or count entries.
- * The pairs are spread over worker contexts of ctx (opt->many_workers of
- * them, each with its own stream, workspace and host thread), every pair
- * running the single-pair solve on its worker, so a pair's result is the
+ * Pairs whose matrix is a single tile (2 <= n <= 256; edge 64, 128 or 256)
+ * are solved in lockstep on a group context of ctx: each outer iteration of
+ * Algorithm 1 is one launch per kernel for all pairs still running (the two
+ * GEMMs, the whole SDSN projection of each pair in one workgroup, the N
+ * update and delta) and one copy of all their states to the host, where
+ * every pair's stop rules are applied; a pair leaves the group when it stops.
+ * A grouped pair's result equals, bit for bit, solving it alone with
+ * opt->tile set to its edge (for n <= 128 that is the default layout).  Pairs
+ * are grouped only with the FRAM variant, stable_iters = 0, profile = 0,
+ * sdsn_mode 0 or 1 and opt->tile 0 or the pair's edge.  The other pairs are
+ * spread over worker contexts of ctx (opt->many_workers of them, each with its
+ * own stream, workspace and host thread), concurrently with the group, every
+ * pair running the single-pair solve on its worker, so its result is the
  * same as when it is solved alone.  The first error stops the call and is
  * returned (later pairs are then left unwritten). */
 fram_status fram_solve_many(fram_ctx* ctx, int count, const double* const* A,
@@ -370,11 +380,11 @@ fram_status fram_solve_many_ex(fram_ctx* ctx, int count, const double* const* A,
 
 /* Device memory the context holds between calls: its workspace (which only
  * grows, to the largest problem solved so far), that of its fram_solve_many
- * workers, and its small fixed buffers.  Pure host bookkeeping. */
+ * workers and group, and its small fixed buffers.  Pure host bookkeeping. */
 size_t fram_resident_bytes(const fram_ctx* ctx);
 
-/* Release the workspace of the context and of its workers (after waiting for
- * their streams); the next call allocates again.  For admission control that
+/* Release the workspace of the context, its workers and its group (after
+ * waiting for their streams); the next call allocates again.  For admission control that
  * must bound the memory held by idle contexts.  NULL is accepted. */
 fram_status fram_trim(fram_ctx* ctx);
 

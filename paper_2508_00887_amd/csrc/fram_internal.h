@@ -61,6 +61,45 @@ inline size_t elem_size(Elem e) { return e == Elem::F32 ? 4 : 2; }
 hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
                           int n, int np, int ld, hipStream_t s, const float* bias = nullptr);
 
+// ---------------------------------------------------------- group launches
+// The per-iteration kernels of many small pairs in one launch each, one job
+// per pair (device arrays of jobs).  Every pair's matrix is a single tile
+// (np == bm), and each job is computed exactly as the corresponding
+// single-pair launch would compute it.
+
+struct GemmJob {  // C = P * Q^T over K = n
+  const void* P;
+  const void* Q;
+  void* C;
+  int ld;      // leading dimension (np)
+  int ktiles;  // gemm_ktiles(e, n)
+};
+int gemm_ktiles(Elem e, int n);
+// All jobs have np == bm.  Output as launch_gemm_nt with the same c_f32.
+hipError_t launch_gemm_group(Elem e, int bm, bool c_f32, const GemmJob* jobs, int count,
+                             hipStream_t s);
+
+struct SdsnJob {  // one projection: statistics of X, then every pass, in place
+  float* X;
+  int n, np;
+  Partials p0, p1;
+  DevState* st;
+};
+// Jobs with np == bm; same iterates as launch_tile_stats + launch_sdsn_chunk.
+hipError_t launch_sdsn_group(int bm, const SdsnJob* jobs, int count, int max_passes,
+                             double theta, double gamma_tol, hipStream_t s);
+
+struct UpdateJob {  // N <- (1-alpha) N + alpha D, the GEMM-type copy, delta
+  const float* D;
+  float* N;
+  void* Nlp;
+  int n, np, nblocks;  // nblocks = update_blocks(n), as the single-pair launch
+  double* part;
+  DevState* st;
+};
+hipError_t launch_update_group(Elem e, const UpdateJob* jobs, int count, int max_blocks,
+                               double alpha, hipStream_t s);
+
 // Tile statistics of an n x n matrix: reads src (ld_src), writes it padded to
 // dst (np x np, ld np, zero padding) unless dst == nullptr or dst == src, and
 // fills `out` (row/col partials, FP64 tile totals, tile maxima).  Also resets

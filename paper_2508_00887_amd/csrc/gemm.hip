@@ -78,12 +78,11 @@ constexpr int kChunks = 8;  // 16-byte chunks per LDS row (128 bytes of K)
 // chunk in 8 different places per row parity.
 __device__ __forceinline__ int swz(int row, int ch) { return ch ^ ((row >> 1) & 7); }
 
+// Output tile (tm, tn) of C = P * Q^T: one workgroup of 256 threads.
 template <Elem E, int BM, bool OUT_F32>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
-                                                      const v4u* __restrict__ Q,
-                                                      void* __restrict__ C,
-                                                      const float* __restrict__ bias, int np,
-                                                      int ld, int ktiles) {
+__device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* __restrict__ Q,
+                                          void* __restrict__ C, const float* __restrict__ bias,
+                                          int ld, int ktiles, int tm, int tn) {
   constexpr int WT = BM / 2;          // wave tile edge
   constexpr int F = WT / 32;          // MFMA blocks per wave tile edge
   constexpr int LOADS = BM * kChunks / 256;
@@ -92,18 +91,6 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int nbn = np / BM;
-  const int bid = blockIdx.x;
-  const int ntiles = gridDim.x;
-  int tm = bid / nbn, tn = bid % nbn;
-  if ((ntiles & 7) == 0 && (nbn & 1) == 0 && ((nbn / 2) & 3) == 0) {
-    // Workgroup bid runs on XCD bid % 8.  XCD x takes the x-th block of the
-    // tile grid cut into 2 x 4 blocks (nbn/2 tile rows by nbn/4 tile columns).
-    const int x = bid & 7, k = bid >> 3;
-    const int bh = nbn / 2, bw = nbn / 4;
-    tm = (x >> 2) * bh + k / bw;
-    tn = (x & 3) * bw + k % bw;
-  }
   const int m0 = tm * BM;
   const int n0 = tn * BM;
   const int wm = wave >> 1, wn = wave & 1;
@@ -216,6 +203,55 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
         }
 }
 
+template <Elem E, int BM, bool OUT_F32>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
+                                                      const v4u* __restrict__ Q,
+                                                      void* __restrict__ C,
+                                                      const float* __restrict__ bias, int np,
+                                                      int ld, int ktiles) {
+  const int nbn = np / BM;
+  const int bid = blockIdx.x;
+  const int ntiles = gridDim.x;
+  int tm = bid / nbn, tn = bid % nbn;
+  if ((ntiles & 7) == 0 && (nbn & 1) == 0 && ((nbn / 2) & 3) == 0) {
+    // Workgroup bid runs on XCD bid % 8.  XCD x takes the x-th block of the
+    // tile grid cut into 2 x 4 blocks (nbn/2 tile rows by nbn/4 tile columns).
+    const int x = bid & 7, k = bid >> 3;
+    const int bh = nbn / 2, bw = nbn / 4;
+    tm = (x >> 2) * bh + k / bw;
+    tn = (x & 3) * bw + k % bw;
+  }
+  gemm_tile<E, BM, OUT_F32>(P, Q, C, bias, ld, ktiles, tm, tn);
+}
+
+// Many independent products (one job each, blockIdx.y), each one tile of
+// edge BM (np == BM): the GEMMs of a group of small pairs in one launch.
+template <Elem E, int BM, bool OUT_F32>
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmJob* __restrict__ jobs) {
+  const GemmJob j = jobs[blockIdx.y];
+  gemm_tile<E, BM, OUT_F32>(static_cast<const v4u*>(j.P), static_cast<const v4u*>(j.Q), j.C,
+                            nullptr, j.ld, j.ktiles, 0, 0);
+}
+
+template <Elem E, bool OUT_F32>
+hipError_t launch_group_e(int bm, const GemmJob* jobs, int count, hipStream_t s) {
+  const dim3 grid(1, count);
+  switch (bm) {
+    case 64:
+      gemm_group_kernel<E, 64, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      break;
+    case 128:
+      gemm_group_kernel<E, 128, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      break;
+    case 256:
+      gemm_group_kernel<E, 256, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <Elem E, bool OUT_F32>
 hipError_t launch_e(int bm, const void* P, const void* Q, void* C, const float* bias, int n,
                     int np, int ld, hipStream_t s) {
@@ -242,6 +278,28 @@ hipError_t launch_e(int bm, const void* P, const void* Q, void* C, const float* 
 }
 
 }  // namespace
+
+int gemm_ktiles(Elem e, int n) {
+  const int kelems = kChunks * (e == Elem::F32 ? 4 : 8);
+  return (n + kelems - 1) / kelems;
+}
+
+hipError_t launch_gemm_group(Elem e, int bm, bool c_f32, const GemmJob* jobs, int count,
+                             hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  switch (e) {
+    case Elem::F32:  // FP32 products are always written as float
+      return launch_group_e<Elem::F32, true>(bm, jobs, count, s);
+    case Elem::BF16:
+      return c_f32 ? launch_group_e<Elem::BF16, true>(bm, jobs, count, s)
+                   : launch_group_e<Elem::BF16, false>(bm, jobs, count, s);
+    case Elem::F16:
+      return c_f32 ? launch_group_e<Elem::F16, true>(bm, jobs, count, s)
+                   : launch_group_e<Elem::F16, false>(bm, jobs, count, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_gemm_nt(Elem e, int bm, const void* P, const void* Q, void* C, bool c_f32,
                           int n, int np, int ld, hipStream_t s, const float* bias) {

@@ -171,16 +171,18 @@ __global__ __launch_bounds__(kT) void cast_f32_kernel(const float* __restrict__ 
 }
 
 // ------------------------------------------------------------------ update
+// Block b of nblocks: a grid-stride share of the rows, and its FP64 partial
+// sums of delta's numerator and denominator in part[2b], part[2b + 1].
 template <Elem E>
-__global__ __launch_bounds__(kT) void update_kernel(const float* __restrict__ D,
-                                                    float* __restrict__ N, void* Nlp, int n,
-                                                    int np, float alpha, double* part) {
+__device__ __forceinline__ void update_body(const float* __restrict__ D, float* __restrict__ N,
+                                            void* Nlp, int n, int np, float alpha, double* part,
+                                            int b, int nblocks) {
   __shared__ double sh[kT];
   const float c1 = 1.0f - alpha;
   double num = 0.0, den = 0.0;
   const int q = np / 4;  // float4 per row
   const size_t total = (size_t)n * q;
-  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
+  for (size_t t = (size_t)b * kT + threadIdx.x; t < total; t += (size_t)nblocks * kT) {
     const size_t i = t / q, c = t % q;
     const size_t idx = i * np + 4 * c;
     const float4 o = *reinterpret_cast<const float4*>(N + idx);
@@ -207,13 +209,28 @@ __global__ __launch_bounds__(kT) void update_kernel(const float* __restrict__ D,
   num = block_sum_256(num, sh);
   den = block_sum_256(den, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = num;
-    part[2 * blockIdx.x + 1] = den;
+    part[2 * b] = num;
+    part[2 * b + 1] = den;
   }
 }
 
-__global__ __launch_bounds__(kT) void delta_final_kernel(const double* part, int nblocks,
-                                                         DevState* st) {
+template <Elem E>
+__global__ __launch_bounds__(kT) void update_kernel(const float* __restrict__ D,
+                                                    float* __restrict__ N, void* Nlp, int n,
+                                                    int np, float alpha, double* part) {
+  update_body<E>(D, N, Nlp, n, np, alpha, part, blockIdx.x, gridDim.x);
+}
+
+// The updates of many pairs (job blockIdx.y), each with its own block count.
+template <Elem E>
+__global__ __launch_bounds__(kT) void update_group_kernel(const UpdateJob* __restrict__ jobs,
+                                                          float alpha) {
+  const UpdateJob j = jobs[blockIdx.y];
+  if ((int)blockIdx.x >= j.nblocks) return;
+  update_body<E>(j.D, j.N, j.Nlp, j.n, j.np, alpha, j.part, blockIdx.x, j.nblocks);
+}
+
+__device__ __forceinline__ void delta_final_body(const double* part, int nblocks, DevState* st) {
   __shared__ double sh[kT];
   double num = 0.0, den = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += kT) {
@@ -227,6 +244,16 @@ __global__ __launch_bounds__(kT) void delta_final_kernel(const double* part, int
     st->dden = den;
     st->delta = den > 0.0 ? sqrt(num) / sqrt(den) : 0.0;
   }
+}
+
+__global__ __launch_bounds__(kT) void delta_final_kernel(const double* part, int nblocks,
+                                                         DevState* st) {
+  delta_final_body(part, nblocks, st);
+}
+
+__global__ __launch_bounds__(kT) void delta_group_kernel(const UpdateJob* __restrict__ jobs) {
+  const UpdateJob j = jobs[blockIdx.x];
+  delta_final_body(j.part, j.nblocks, j.st);
 }
 
 // ------------------------------------------------------------------ validation
@@ -455,6 +482,26 @@ hipError_t launch_update(Elem e, const float* D, float* N, void* Nlp, int n, int
       break;
   }
   delta_final_kernel<<<1, kT, 0, s>>>(part, nblocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_group(Elem e, const UpdateJob* jobs, int count, int max_blocks,
+                               double alpha, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  if (count > 65535 || max_blocks < 1) return hipErrorInvalidValue;
+  const dim3 grid(max_blocks, count);
+  switch (e) {
+    case Elem::F32:
+      update_group_kernel<Elem::F32><<<grid, kT, 0, s>>>(jobs, (float)alpha);
+      break;
+    case Elem::BF16:
+      update_group_kernel<Elem::BF16><<<grid, kT, 0, s>>>(jobs, (float)alpha);
+      break;
+    case Elem::F16:
+      update_group_kernel<Elem::F16><<<grid, kT, 0, s>>>(jobs, (float)alpha);
+      break;
+  }
+  delta_group_kernel<<<count, kT, 0, s>>>(jobs);
   return hipGetLastError();
 }
 

@@ -57,8 +57,10 @@ struct fram_ctx {
   // outer iteration (host copies).
   std::vector<int32_t> arg_cur, arg_prev;
   // fram_solve_many: worker contexts (own stream and workspace each), made on
-  // first use and kept until fram_destroy.
+  // first use and kept until fram_destroy, and the context of the lockstep
+  // group of small pairs.
   std::vector<fram_ctx*> workers;
+  fram_ctx* group = nullptr;
 };
 
 namespace {
@@ -943,6 +945,224 @@ fram_status solve_dev_impl(fram_ctx* c, const double* dA, const double* dB, cons
   return r;
 }
 
+// ---------------------------------------------------------------------------
+// Lockstep group of small pairs (fram_solve_many).  Every pair whose matrix
+// is a single tile (n <= 256, edge 64, 128 or 256) runs Algorithm 1 in step
+// with the others: each outer iteration is one launch per kernel for all
+// active pairs (the two GEMMs, the whole SDSN projection -- statistics and
+// every pass in one workgroup per pair --, the N update and delta), and one
+// copy of all pairs' states back to the host, where each pair's stop rules
+// are applied exactly as in run_solve; finished pairs leave the group.  Each
+// job computes what the single-pair launch computes, so a pair's result
+// equals, bit for bit, solving it alone with fram_options.tile set to its
+// edge.  Small pairs on the single-pair path are bound by launch and
+// host-synchronisation latency (two state reads per outer iteration); here
+// the latency is shared by the whole group.
+
+int group_edge(int n) { return n <= 64 ? 64 : (n <= 128 ? 128 : 256); }
+
+bool group_eligible(int n, const fram_options& o) {
+  return n >= 2 && n <= 256 && o.variant == 0 && o.stable_iters == 0 && o.profile == 0 &&
+         o.sdsn_mode != 2 && (o.tile == 0 || o.tile == group_edge(n));
+}
+
+void shift_layout(Layout& L, size_t b) {
+  for (size_t* f : {&L.A64, &L.B64, &L.K64, &L.Kp, &L.Alp, &L.Blp, &L.W, &L.N, &L.Nlp, &L.X,
+                    &L.Nprev, &L.rowp[0], &L.rowp[1], &L.colp[0], &L.colp[1], &L.tot[0],
+                    &L.tot[1], &L.tmax[0], &L.tmax[1], &L.upd, &L.mx, &L.obj, &L.sigma, &L.lap,
+                    &L.state})
+    *f += b;
+}
+
+fram_status solve_group(fram_ctx* c, const std::vector<int>& pairs, const double* const* A,
+                        const double* const* B, const int* n, double theta, int iters,
+                        double tol, const fram_options& o, int32_t* const* perm_out,
+                        double* objective_out, fram_stats* stats) {
+  const int G = (int)pairs.size();
+  if (G == 0) return FRAM_OK;
+  const Elem e = (Elem)o.prec;
+  std::vector<Layout> Ls(G);
+  size_t off = 0;
+  for (int g = 0; g < G; ++g) {
+    const int m = n[pairs[g]];
+    Ls[g] = plan(m, e, group_edge(m), Use::Solve);
+    shift_layout(Ls[g], off);
+    off += align_up(Ls[g].total);
+  }
+  const size_t states_off = off;
+  off += align_up((size_t)G * sizeof(DevState));
+  const size_t jobs_off = off;
+  const size_t jobs_bytes =
+      (size_t)G * (2 * sizeof(fram::GemmJob) + sizeof(fram::SdsnJob) + sizeof(fram::UpdateJob));
+  off += align_up(jobs_bytes);
+  if (c->budget != 0 && off > c->budget) {
+    c->err = "the group's workspace exceeds the HBM budget";
+    return FRAM_ENOMEM;
+  }
+  fram_status r = ensure_device(c);
+  if (r != FRAM_OK) return r;
+  r = ensure_ws(c, off);
+  if (r != FRAM_OK) return r;
+  hipStream_t s = c->stream;
+  DevState* states = at<DevState>(c, states_off);
+  HIPCHK(fram::launch_zero(states, (size_t)G * sizeof(DevState), s));
+
+  // Algorithm 1, steps 1-3 for every pair, as in run_solve.
+  for (int g = 0; g < G; ++g) {
+    const Layout& L = Ls[g];
+    const int p = pairs[g], m = n[p];
+    const size_t np2 = (size_t)L.np * L.np;
+    double* dA = at<double>(c, L.A64);
+    double* dB = at<double>(c, L.B64);
+    HIPCHK(hipMemcpyAsync(dA, A[p], (size_t)m * m * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dB, B[p], (size_t)m * m * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(fram::launch_maxes(dA, dB, m, at<double>(c, L.mx), L.nmax, &states[g], s));
+    HIPCHK(fram::launch_cast_scaled(e, dA, m, at<void>(c, L.Alp), L.np, &states[g], 0, s));
+    HIPCHK(fram::launch_cast_scaled(e, dB, m, at<void>(c, L.Blp), L.np, &states[g], 1, s));
+    HIPCHK(fram::launch_zero(at<float>(c, L.N), np2 * 4, s));
+    if (e != Elem::F32) HIPCHK(fram::launch_zero(at<void>(c, L.Nlp), np2 * fram::elem_size(e), s));
+  }
+
+  struct PairRun {
+    int it = 0, total_passes = 0, last_passes = 0, max_passes = 0, stall = 0;
+    bool capped = false, converged = false, stalled = false;
+    double gamma = 0.0, delta = 0.0, dmin = 0.0;
+  };
+  std::vector<PairRun> run(G);
+  std::vector<int> active(G);
+  for (int g = 0; g < G; ++g) active[g] = g;
+  std::vector<DevState> hs(G);
+  std::vector<char> stage(jobs_bytes);
+  char* djobs = at<char>(c, jobs_off);
+  const bool watch_stall = o.stall_iters > 0;
+  for (int it = 1; it <= iters && !active.empty(); ++it) {
+    // Job tables of the active pairs: GEMM and SDSN jobs grouped by edge,
+    // update jobs for all.
+    const int A_ = (int)active.size();
+    fram::GemmJob* g1 = reinterpret_cast<fram::GemmJob*>(stage.data());
+    fram::GemmJob* g2 = g1 + A_;
+    fram::SdsnJob* sj = reinterpret_cast<fram::SdsnJob*>(g2 + A_);
+    fram::UpdateJob* uj = reinterpret_cast<fram::UpdateJob*>(sj + A_);
+    int cnt[3] = {0, 0, 0}, first[3] = {0, 0, 0};
+    std::vector<int> order;
+    order.reserve(A_);
+    for (int k = 0; k < 3; ++k) {
+      first[k] = (int)order.size();
+      for (int g : active)
+        if (group_edge(n[pairs[g]]) == (64 << k)) order.push_back(g);
+      cnt[k] = (int)order.size() - first[k];
+    }
+    int max_blocks = 1;
+    for (int q = 0; q < A_; ++q) {
+      const int g = order[q];
+      const Layout& L = Ls[g];
+      const int m = n[pairs[g]];
+      void* Nlp = (e == Elem::F32) ? at<void>(c, L.N) : at<void>(c, L.Nlp);
+      g1[q] = {at<void>(c, L.Blp), Nlp, at<void>(c, L.W), L.np, fram::gemm_ktiles(e, m)};
+      g2[q] = {at<void>(c, L.Alp), at<void>(c, L.W), at<void>(c, L.X), L.np,
+               fram::gemm_ktiles(e, m)};
+      sj[q] = {at<float>(c, L.X), m, L.np, partials(c, L, 0), partials(c, L, 1), &states[g]};
+      uj[q] = {at<float>(c, L.X), at<float>(c, L.N), Nlp, m, L.np, L.nupd, at<double>(c, L.upd),
+               &states[g]};
+      max_blocks = std::max(max_blocks, L.nupd);
+    }
+    const size_t used = (size_t)A_ * (2 * sizeof(fram::GemmJob) + sizeof(fram::SdsnJob) +
+                                      sizeof(fram::UpdateJob));
+    // The tables are rewritten each iteration after the previous iteration's
+    // launches have finished (the state copy below synchronises).
+    HIPCHK(hipMemcpyAsync(djobs, stage.data(), used, hipMemcpyHostToDevice, s));
+    const fram::GemmJob* d1 = reinterpret_cast<const fram::GemmJob*>(djobs);
+    const fram::GemmJob* d2 = d1 + A_;
+    const fram::SdsnJob* ds = reinterpret_cast<const fram::SdsnJob*>(d2 + A_);
+    const fram::UpdateJob* du = reinterpret_cast<const fram::UpdateJob*>(ds + A_);
+    for (int k = 0; k < 3; ++k)  // Step 5: W = B N^T, X = A W^T
+      HIPCHK(fram::launch_gemm_group(e, 64 << k, false, d1 + first[k], cnt[k], s));
+    for (int k = 0; k < 3; ++k)
+      HIPCHK(fram::launch_gemm_group(e, 64 << k, true, d2 + first[k], cnt[k], s));
+    for (int k = 0; k < 3; ++k)  // Step 6: D = SDSN(X, theta)
+      HIPCHK(fram::launch_sdsn_group(64 << k, ds + first[k], cnt[k], o.sdsn_max, theta,
+                                     o.gamma_tol, s));
+    // Steps 7-8: N update and delta.
+    HIPCHK(fram::launch_update_group(e, du, A_, max_blocks, o.alpha, s));
+    HIPCHK(hipMemcpyAsync(hs.data(), states, (size_t)G * sizeof(DevState),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> still;
+    still.reserve(A_);
+    for (int g : active) {
+      PairRun& pr = run[g];
+      const DevState& h = hs[g];
+      const int p = pairs[g];
+      pr.it = it;
+      if (!h.done) {
+        c->err = "pair " + std::to_string(p) + ": SDSN loop ended without completion flag";
+        return FRAM_EDEVICE;
+      }
+      pr.gamma = h.gamma;
+      pr.total_passes += h.passes;
+      pr.last_passes = h.passes;
+      pr.max_passes = std::max(pr.max_passes, h.passes);
+      pr.capped = pr.capped || ((h.passes >= o.sdsn_max) && !(h.gamma <= o.gamma_tol));
+      if (!std::isfinite(h.gamma)) {
+        c->err = "pair " + std::to_string(p) + ": non-finite gamma in SDSN";
+        return FRAM_ENUMERIC;
+      }
+      bool finished = it == iters;
+      if (tol > 0.0 || watch_stall || it == iters) {
+        pr.delta = h.delta;
+        if (!std::isfinite(pr.delta)) {
+          c->err = "pair " + std::to_string(p) + ": non-finite delta";
+          return FRAM_ENUMERIC;
+        }
+        if (pr.delta <= tol) {
+          pr.converged = true;
+          finished = true;
+        } else if (watch_stall && pr.delta <= o.stall_delta) {
+          pr.stall = (pr.dmin > 0.0 && pr.delta >= pr.dmin) ? pr.stall + 1 : 0;
+          pr.dmin = (pr.dmin > 0.0) ? std::min(pr.dmin, pr.delta) : pr.delta;
+          if (pr.stall >= o.stall_iters) {
+            pr.converged = true;
+            pr.stalled = true;
+            finished = true;
+          }
+        }
+      }
+      if (!finished) still.push_back(g);
+    }
+    active.swap(still);
+  }
+
+  // Step 10 and the objective, pair by pair (as run_solve does).
+  Prof prof{0, c, s, 0.0f};
+  for (int g = 0; g < G; ++g) {
+    const Layout& L = Ls[g];
+    const int p = pairs[g], m = n[p];
+    fram_stats st{};
+    int lap_paths = 0;
+    r = finish_discretise(c, L, m, at<double>(c, L.A64), at<double>(c, L.B64), NodeTerm{},
+                          at<float>(c, L.N), at<int32_t>(c, L.sigma), &states[g], s, perm_out[p],
+                          &objective_out[p], &lap_paths, prof, &st);
+    if (r != FRAM_OK) {
+      c->err = "pair " + std::to_string(p) + ": " + c->err;
+      return r;
+    }
+    const PairRun& pr = run[g];
+    st.outer_iters = pr.it;
+    st.sdsn_passes = pr.total_passes;
+    st.sdsn_passes_last = pr.last_passes;
+    st.sdsn_passes_max = pr.max_passes;
+    st.converged = pr.converged ? 1 : 0;
+    st.sdsn_capped = pr.capped ? 1 : 0;
+    st.lap_paths = lap_paths;
+    st.stalled = pr.stalled ? 1 : 0;
+    st.gemm_tile = L.bm;
+    st.delta = pr.delta;
+    st.gamma = pr.gamma;
+    if (stats) stats[p] = st;
+  }
+  return FRAM_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -987,6 +1207,7 @@ fram_status fram_create(fram_ctx** out, int device, size_t hbm_budget_bytes) {
 void fram_destroy(fram_ctx* c) {
   if (!c) return;
   for (fram_ctx* w : c->workers) fram_destroy(w);
+  if (c->group) fram_destroy(c->group);
   if (c->inited) {
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     (void)hipSetDevice(c->device);
@@ -1005,6 +1226,7 @@ size_t fram_resident_bytes(const fram_ctx* c) {
   if (!c) return 0;
   size_t b = c->ws_bytes + (c->sync ? fram::kOnchipSyncBytes : 0);
   for (const fram_ctx* w : c->workers) b += fram_resident_bytes(w);
+  if (c->group) b += fram_resident_bytes(c->group);
   return b;
 }
 
@@ -1012,6 +1234,10 @@ fram_status fram_trim(fram_ctx* c) {
   if (!c) return FRAM_OK;
   for (fram_ctx* w : c->workers) {
     const fram_status r = fram_trim(w);
+    if (r != FRAM_OK) return r;
+  }
+  if (c->group) {
+    const fram_status r = fram_trim(c->group);
     if (r != FRAM_OK) return r;
   }
   if (c->ws) {
@@ -1329,10 +1555,26 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
       single.push_back(p);
     }
   }
-  // Every pair runs the single-pair path: up to o.many_workers pairs at a
-  // time, each on a worker context with its own stream and workspace (one
-  // host thread per worker), largest pairs first.  Each pair's result is that
-  // of solving it alone: nothing is shared between the workers but the device.
+  // Pairs whose matrix is a single tile run in the lockstep group (its own
+  // context and host thread); the others run the single-pair path, up to
+  // o.many_workers pairs at a time, each on a worker context with its own
+  // stream and workspace (one host thread per worker), largest pairs first.
+  // Nothing is shared between the group and the workers but the device.
+  std::vector<int> grouped, rest;
+  for (int p : single) (group_eligible(n[p], o) ? grouped : rest).push_back(p);
+  single.swap(rest);
+  std::thread group_thread;
+  fram_status group_status = FRAM_OK;
+  if (!grouped.empty()) {
+    if (c->group == nullptr) {
+      r = fram_create(&c->group, c->device, c->budget == 0 ? 0 : c->budget / 2);
+      if (r != FRAM_OK) return r;
+    }
+    group_thread = std::thread([&] {
+      group_status = solve_group(c->group, grouped, A, B, n, lambda, iters, tol, o, perm_out,
+                                 objective_out, stats);
+    });
+  }
   if (!single.empty()) {
     std::stable_sort(single.begin(), single.end(), [&](int x, int y) { return n[x] > n[y]; });
     const int nw = (int)std::min<size_t>((size_t)o.many_workers, single.size());
@@ -1374,7 +1616,15 @@ fram_status fram_solve_many_ex(fram_ctx* c, int count, const double* const* A,
       for (int t = 0; t < nw; ++t) th.emplace_back(work, c->workers[t]);
       for (auto& t : th) t.join();
     }
-    if (first != FRAM_OK) return first;
+    if (first != FRAM_OK) {
+      if (group_thread.joinable()) group_thread.join();
+      return first;
+    }
+  }
+  if (group_thread.joinable()) group_thread.join();
+  if (group_status != FRAM_OK) {
+    c->err = "lockstep group: " + c->group->err;
+    return group_status;
   }
   const double ms = now_ms() - t0;
   if (stats)

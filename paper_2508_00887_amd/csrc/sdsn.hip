@@ -53,8 +53,9 @@ struct TileArgs {
 // wave is read before the first is written, so a pass costs one memory round
 // trip instead of one per row; rows and columns past n are read (zero
 // padding) and written back as zeros.
+// Tile (bm, bn) of an nb x nb tile grid.
 template <int BM, bool PASS, bool WHOLE = false>
-__device__ __forceinline__ bool tile_body(const TileArgs& a) {
+__device__ __forceinline__ bool tile_body(const TileArgs& a, int bm, int bn, int nb) {
   constexpr int NT = TileShape<BM>::NT;
   constexpr int LPR = TileShape<BM>::LPR;      // lanes per tile row
   constexpr int RPW = TileShape<BM>::RPW;      // tile rows per wave step
@@ -69,7 +70,6 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
   const int lane = tid & 63;
   // Wave index as a scalar: row bounds then stay in SGPRs.
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int bn = blockIdx.x, bm = blockIdx.y, nb = gridDim.x;
   const int n = a.n, np = a.np;
   DevState* st = a.st;
 
@@ -232,7 +232,7 @@ __device__ __forceinline__ bool tile_body(const TileArgs& a) {
 
 template <int BM, bool PASS>
 __global__ __launch_bounds__(4 * BM) void tile_kernel(TileArgs a) {
-  (void)tile_body<BM, PASS>(a);
+  (void)tile_body<BM, PASS>(a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // Passes a.k .. k_last of a projection whose matrix is a single tile, in one
@@ -249,7 +249,40 @@ __global__ __launch_bounds__(4 * BM) void tile_chunk_kernel(TileArgs a, Partials
     a.out = (k & 1) ? p1 : p0;
     // Whole-tile loads pay off while the wave's rows fit in registers next to
     // everything else (BM <= 128); at 256 they spill.
-    if (tile_body<BM, true, (BM <= 128)>(a)) break;
+    if (tile_body<BM, true, (BM <= 128)>(a, 0, 0, 1)) break;
+    __syncthreads();
+  }
+}
+
+// One projection per job (blockIdx.x), each a single tile: the statistics
+// pass of tile_kernel<BM, false> (dst = nullptr) and then every pass of
+// tile_chunk_kernel, in one workgroup -- the same iterates as those two
+// launches.
+template <int BM>
+__global__ __launch_bounds__(4 * BM) void sdsn_group_kernel(const SdsnJob* __restrict__ jobs,
+                                                            int max_passes, double theta,
+                                                            double gamma_tol) {
+  const SdsnJob j = jobs[blockIdx.x];
+  TileArgs a{};
+  a.src = j.X;
+  a.ld_src = j.np;
+  a.dst = nullptr;
+  a.n = j.n;
+  a.np = j.np;
+  a.out = j.p0;
+  a.st = j.st;
+  (void)tile_body<BM, false>(a, 0, 0, 1);
+  __syncthreads();
+  a.dst = j.X;
+  a.max_passes = max_passes;
+  a.theta = theta;
+  a.gamma_tol = gamma_tol;
+  const int k_last = max_passes + 1;
+  for (int k = 1; k <= k_last; ++k) {
+    a.k = k;
+    a.in = ((k - 1) & 1) ? j.p1 : j.p0;
+    a.out = (k & 1) ? j.p1 : j.p0;
+    if (tile_body<BM, true, (BM <= 128)>(a, 0, 0, 1)) break;
     __syncthreads();
   }
 }
@@ -316,6 +349,25 @@ hipError_t launch_sdsn_chunk(int bm, float* X, int n, int np, Partials p0, Parti
       break;
     case 256:
       tile_chunk_kernel<256><<<one, dim3(1024), 0, s>>>(a, p0, p1, k_last);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sdsn_group(int bm, const SdsnJob* jobs, int count, int max_passes,
+                             double theta, double gamma_tol, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  switch (bm) {
+    case 64:
+      sdsn_group_kernel<64><<<count, 256, 0, s>>>(jobs, max_passes, theta, gamma_tol);
+      break;
+    case 128:
+      sdsn_group_kernel<128><<<count, 512, 0, s>>>(jobs, max_passes, theta, gamma_tol);
+      break;
+    case 256:
+      sdsn_group_kernel<256><<<count, 1024, 0, s>>>(jobs, max_passes, theta, gamma_tol);
       break;
     default:
       return hipErrorInvalidValue;

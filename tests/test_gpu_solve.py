@@ -24,8 +24,10 @@ GOLDEN = pathlib.Path(__file__).resolve().parent / "golden"
 # The batched kernel (one workgroup per pair, fram_solve_many for n <= 512)
 # made a GPU memory access fault on its first test run on the device
 # (8 pairs, FP32); a CPU emulation of the same launch finds no
-# out-of-bounds access, so the cause is not shown and the kernel stays
-# switched off.  These tests expect the batched kernel (gemm_tile 32).
+# out-of-bounds access, so the cause is not shown and the kernel was
+# removed.  These tests expect that kernel (gemm_tile 32) and stay skipped;
+# fram_solve_many's lockstep group of small pairs has its own tests below
+# (test_group_*).
 BATCHED_OFF = pytest.mark.skip(
     reason="batched kernel switched off: it faulted the GPU on its first run and the cause "
            "is not found (a CPU emulation of the launch runs clean)")
@@ -262,6 +264,27 @@ def test_onchip_barrier_aborts_fall_back_inside_solves(ctx, prec):
     assert o1 == o2 and s1["sdsn_passes"] == s2["sdsn_passes"]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_solve_many_group_equals_single_solves(ctx, prec):
+    # Pairs whose matrix is one tile (n <= 256) run in the lockstep group;
+    # each must equal solving it alone with its one-tile edge.  Larger pairs
+    # run the single-pair path (default layout), concurrently with the group.
+    sizes = [2, 17, 64, 65, 100, 128, 129, 200, 256, 257, 300]
+    pairs = [synth.make_pair(m, 0.3, 0.05, 6100 + m) for m in sizes]
+    perms, objs, sts = ctx.solve_many([q.A for q in pairs], [q.B for q in pairs], iters=60,
+                                      tol=1e-6, prec=prec, stall_iters=3)
+    for q, p, o, st in zip(pairs, perms, objs, sts):
+        edge = 64 if q.n <= 64 else 128 if q.n <= 128 else 256
+        kw = dict(tile=edge) if q.n <= 256 else {}
+        p1, o1, s1 = ctx.solve(q.A, q.B, iters=60, tol=1e-6, prec=prec, stall_iters=3, **kw)
+        np.testing.assert_array_equal(p, p1)
+        assert o == o1, q.n
+        for key in ("outer_iters", "sdsn_passes", "sdsn_passes_max", "converged", "stalled",
+                    "lap_paths", "gemm_tile"):
+            assert st[key] == s1[key], (q.n, key, st[key], s1[key])
+        assert st["delta"] == s1["delta"] and st["gamma"] == s1["gamma"], q.n
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_stability_stop_matches_oracle(ctx, seed):
     pr = next(synth.config_pairs(0, [seed]))
@@ -296,7 +319,8 @@ def test_n4000_stability_stop_accuracy_gate(ctx, prec):
 
 def test_solve_many_equals_single_solves(ctx):
     # fram_solve_many returns, pair by pair, what fram_solve returns for that
-    # pair alone (n = 1 answered on the host).
+    # pair alone with the one-tile layout the lockstep group uses (n = 1
+    # answered on the host).
     pairs = _small_batch(4, 33, n_hi=200)
     one = np.zeros((1, 1))
     As = [one] + [p.A for p in pairs]
@@ -304,7 +328,16 @@ def test_solve_many_equals_single_solves(ctx):
     perms, objs, stats = ctx.solve_many(As, Bs, iters=30, prec="bf16")
     assert list(perms[0]) == [0] and objs[0] == 0.0
     for pr, perm, obj, st in zip(pairs, perms[1:], objs[1:], stats[1:]):
-        p1, o1, s1 = ctx.solve(pr.A, pr.B, iters=30, prec="bf16")
+        edge = 64 if pr.n <= 64 else 128 if pr.n <= 128 else 256
+        p1, o1, s1 = ctx.solve(pr.A, pr.B, iters=30, prec="bf16", tile=edge)
+        np.testing.assert_array_equal(perm, p1)
+        assert obj == o1 and st["sdsn_passes"] == s1["sdsn_passes"]
+    # Options the group does not take (here a fixed tile that is not the
+    # pair's edge) send every pair down the single-pair path: the default
+    # solve's result.
+    perms, objs, stats = ctx.solve_many(As[1:], Bs[1:], iters=30, prec="bf16", tile=64)
+    for pr, perm, obj, st in zip(pairs, perms, objs, stats):
+        p1, o1, s1 = ctx.solve(pr.A, pr.B, iters=30, prec="bf16", tile=64)
         np.testing.assert_array_equal(perm, p1)
         assert obj == o1 and st["sdsn_passes"] == s1["sdsn_passes"]
 
@@ -428,6 +461,62 @@ def test_concurrent_onchip_solves_equal_solving_alone(ctx):
         np.testing.assert_array_equal(perm, p1)
         assert obj == o1 and st["sdsn_passes"] == s1["sdsn_passes"]
         assert st["sdsn_onchip"] + st["sdsn_fallbacks"] == 20
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_group_pairs_match_oracle(ctx, prec):
+    # The lockstep group (every pair here has n <= 160: one tile) against the
+    # FP64 oracle: FP32 GEMMs give the oracle's permutation, BF16 the accuracy
+    # gate.
+    pairs = _small_batch(8, 31)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=60,
+                                        prec=prec)
+    for pr, perm, obj, st in zip(pairs, perms, objs, stats):
+        s_or, obj_or, _, _ = O.solve(pr.A, pr.B, iters=60)
+        check_perm(perm, pr.n)
+        assert st["outer_iters"] == 60 and st["gemm_tile"] >= pr.n
+        assert abs(obj - host_objective(pr.A, pr.B, perm)) <= 1e-12 * abs(obj)
+        if prec == "fp32":
+            np.testing.assert_array_equal(perm, s_or)
+            assert abs(obj - obj_or) <= 1e-5 * abs(obj_or)
+        else:
+            assert abs(obj - obj_or) <= 1e-3 * abs(obj_or)
+            assert O.accuracy(perm, pr.perm) >= O.accuracy(s_or, pr.perm) - 0.005
+
+
+def test_group_result_is_the_same_alone_and_in_the_mix(ctx):
+    # 40 pairs up to n = 300: the grouped ones (n <= 256) and the single-pair
+    # ones give the same result in the mix as in a call of their own.
+    pairs = _small_batch(40, 32, n_hi=300)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=40,
+                                        tol=1e-6, stall_iters=3)
+    for q in (0, 7, 39) + tuple(i for i, p in enumerate(pairs) if p.n > 256)[:2]:
+        p1, o1, s1 = ctx.solve_many([pairs[q].A], [pairs[q].B], iters=40, tol=1e-6,
+                                    stall_iters=3)
+        np.testing.assert_array_equal(p1[0], perms[q])
+        assert o1[0] == objs[q]
+        assert s1[0]["sdsn_passes"] == stats[q]["sdsn_passes"]
+        assert s1[0]["outer_iters"] == stats[q]["outer_iters"]
+
+
+def test_group_honours_the_stall_rule(ctx):
+    # BF16 delta levels off above tol = 1e-9: once it is below stall_delta
+    # (1e-3) the delta-stall rule ends a grouped pair before the cap, each at
+    # its own iteration; a pair whose delta stays above stall_delta runs to the
+    # cap.  The results meet the accuracy gate against the FP64 oracle.
+    pairs = _small_batch(6, 34, n_hi=250)
+    perms, objs, stats = ctx.solve_many([p.A for p in pairs], [p.B for p in pairs], iters=100,
+                                        tol=1e-9, prec="bf16", stall_iters=3)
+    assert any(st["stalled"] == 1 for st in stats)
+    assert len({st["outer_iters"] for st in stats}) > 1
+    for pr, perm, obj, st in zip(pairs, perms, objs, stats):
+        if st["outer_iters"] < 100:
+            assert st["converged"] == 1 and (st["stalled"] == 1 or st["delta"] <= 1e-9)
+        else:
+            assert st["delta"] > 1e-3, (pr.n, st["delta"])
+        s_or, obj_or, _, _ = O.solve(pr.A, pr.B, iters=100, tol=1e-9)
+        assert abs(obj - obj_or) <= 1e-3 * abs(obj_or)
+        assert O.accuracy(perm, pr.perm) >= O.accuracy(s_or, pr.perm) - 0.005
 
 
 @BATCHED_OFF
