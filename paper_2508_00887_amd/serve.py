@@ -6,13 +6,19 @@ of every request in flight overlap on the device.  A request is admitted the
 moment a slot is free and its device workspace fits the HBM budget that is
 still free; it is never held back for other requests.
 
-* requests with n <= ``small_n`` are taken by the small slots, and by a large
-  slot that finds no large request waiting;
+* requests whose matrix is one tile (2 <= n <= ``group_n``, 256) are taken by
+  the group slot in batches: every such request waiting (up to
+  ``group_max``) is solved in one fram_solve_many call, whose lockstep group
+  runs all of them with one launch per kernel per outer iteration;
+* other requests with n <= ``small_n`` are taken by the small slots, and by a
+  large slot that finds no large request waiting;
 * larger requests are taken by the large slots only, so a burst of large
   requests cannot hold up the small ones.
 
-Every request runs exactly the single-pair solve (fram_solve_ex), so its
-result is the same whether it ran alone or in the mix.  Latency is measured
+A slot request runs exactly the single-pair solve (fram_solve_ex) and a
+grouped one the lockstep group, whose result equals, bit for bit, the
+single-pair solve with the request's one-tile edge as tile: either way a
+request's result is the same whether it ran alone or in the mix.  Latency is measured
 from a request's arrival to the moment its result is back on the host.  The
 loop is plain Python around native calls (ctypes releases the GIL during each
 call, so the slots run concurrently).
@@ -102,16 +108,21 @@ class Budget:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 4,
-                 small_workers: int = 8, small_n: int = 512, prec: str = "bf16",
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, large_workers: int = 12,
+                 small_workers: int = 2, small_n: int = 512, prec: str = "bf16",
                  theta: float = 2.0, iters: int = 100, tol: float = 1e-6,
-                 stall_iters: int = 3, device: int = 0, context_factory=None):
+                 stall_iters: int = 3, device: int = 0, context_factory=None,
+                 group_n: int = 256, group_max: int = 64):
         if large_workers < 1 or small_workers < 0:
             raise ValueError("need at least one large slot and no negative slot count")
+        if not 0 <= group_n <= 256 or group_max < 1:
+            raise ValueError("group_n must be in [0, 256] (0: no group slot), group_max >= 1")
         self.small_n = small_n
+        self.group_n, self.group_max = group_n, group_max
         self.opts = dict(prec=prec, stall_iters=stall_iters)
         self.theta, self.iters, self.tol = theta, iters, tol
         self.budget = Budget(hbm_budget_bytes)
+        self.q_group: deque[Request] = deque()
         self.q_small: deque[Request] = deque()
         self.q_large: deque[Request] = deque()
         self.cv = threading.Condition()
@@ -123,6 +134,11 @@ class Server:
         self.slots += [(f"large{i}", make(device), True) for i in range(large_workers)]
         self.threads = [threading.Thread(target=self._slot_loop, args=(name, c, large),
                                          daemon=True) for name, c, large in self.slots]
+        if group_n > 0:
+            gc = make(device)
+            self.slots.append(("group0", gc, False))
+            self.threads.append(threading.Thread(target=self._group_loop, args=("group0", gc),
+                                                 daemon=True))
 
     # ------------------------------------------------------------- clock
     def now(self) -> float:
@@ -144,9 +160,19 @@ class Server:
         for t in self.threads:
             t.start()
 
+    def _grouped(self, n: int) -> bool:
+        return 2 <= n <= self.group_n
+
+    @staticmethod
+    def _edge(n: int) -> int:
+        return 64 if n <= 64 else (128 if n <= 128 else 256)
+
     def submit(self, req: Request):
         with self.cv:
-            (self.q_small if req.n <= self.small_n else self.q_large).append(req)
+            if self._grouped(req.n):
+                self.q_group.append(req)
+            else:
+                (self.q_small if req.n <= self.small_n else self.q_large).append(req)
             self.cv.notify_all()
 
     def shutdown(self):
@@ -250,6 +276,70 @@ class Server:
             if slot["held"]:
                 self.budget.release(slot["held"])
 
+    def _take_group(self, slot: dict) -> list[Request] | None:
+        """Every grouped request waiting (oldest first, up to group_max), or
+        None once stopped and drained."""
+        with self.cv:
+            while True:
+                if self.q_group:
+                    batch = []
+                    while self.q_group and len(batch) < self.group_max:
+                        batch.append(self.q_group.popleft())
+                    return batch
+                if self.stop.is_set():
+                    return None
+                if self.budget.waiting and slot["held"] > self.FIXED:
+                    self.cv.release()
+                    try:
+                        self._trim(slot)
+                    finally:
+                        self.cv.acquire()
+                    continue
+                self.cv.wait(0.01)
+
+    def _group_loop(self, name: str, ctx):
+        slot = {"ctx": ctx, "held": 0}
+        try:
+            while True:
+                batch = self._take_group(slot)
+                if batch is None:
+                    return
+                try:
+                    # A grouped pair's workspace is at most that of its edge.
+                    need = sum(self._bytes(self._edge(r.n)) for r in batch)
+                except Exception as e:  # noqa: BLE001 - recorded on the requests
+                    for r in batch:
+                        r.error = f"{type(e).__name__}: {e}"
+                        self._finish(r, None, float("nan"), None, name)
+                    continue
+                need = min(need, self.budget.total - self.FIXED)
+                if not self._reserve(slot, need):
+                    return
+                try:
+                    perms, objs, sts = ctx.solve_many([r.A for r in batch], [r.B for r in batch],
+                                                      theta=self.theta, iters=self.iters,
+                                                      tol=self.tol, **self.opts)
+                except Exception:  # noqa: BLE001 - one request spoils the call
+                    # The call stops at its first failing pair: solve the
+                    # batch one by one (each with its edge as tile, which is
+                    # what the group computes), so only the failing requests
+                    # carry an error.
+                    for r in batch:
+                        try:
+                            p_, o_, st = ctx.solve(r.A, r.B, theta=self.theta, iters=self.iters,
+                                                   tol=self.tol, tile=self._edge(r.n),
+                                                   **self.opts)
+                        except Exception as e:  # noqa: BLE001 - recorded on the request
+                            r.error = f"{type(e).__name__}: {e}"
+                            p_, o_, st = None, float("nan"), None
+                        self._finish(r, p_, o_, st, name)
+                    continue
+                for r, p_, o_, st in zip(batch, perms, objs, sts):
+                    self._finish(r, p_, o_, st, name)
+        finally:
+            if slot["held"]:
+                self.budget.release(slot["held"])
+
     # ------------------------------------------------------------- trace replay
     def replay(self, requests: list[Request], timeout_s: float = 600.0) -> list[Request]:
         """Submit each request at its arrival time; wait for all results."""
@@ -291,4 +381,5 @@ def summarize(done: list[Request], warmup_s: float, duration_s: float,
         solves_per_s=len(meas) / max(1e-9, last - warmup_s),
         offered_per_s=len(meas) / duration_s,
         by_small_slots=sum(1 for r in meas if r.worker.startswith("small")),
+        by_group=sum(1 for r in meas if r.worker.startswith("group")),
     )

@@ -40,6 +40,12 @@ class FakeContext:
         p, o = self._answer(A)
         return p, o, {"outer_iters": 1}
 
+    def solve_many(self, As, Bs, **kw):
+        self.calls.append(("solve_many", len(As), kw))
+        self._work(sum(A.shape[0] ** 2 for A in As) // 4)
+        ans = [self._answer(A) for A in As]
+        return [a[0] for a in ans], [a[1] for a in ans], [{"outer_iters": 1} for _ in As]
+
     def close(self):
         pass
 
@@ -73,7 +79,7 @@ def test_server_routes_requests_to_slots_and_completes_everything():
     FakeContext.peak = 0
     reqs = _trace(120, 400.0, 1)
     srv = Server(hbm_budget_bytes=1 << 40, large_workers=2, small_workers=3, small_n=256,
-                 context_factory=FakeContext)
+                 context_factory=FakeContext, group_n=0)
     done = srv.replay(reqs, timeout_s=60)
     assert len(done) == len(reqs)
     for r in done:
@@ -90,6 +96,26 @@ def test_server_routes_requests_to_slots_and_completes_everything():
     assert FakeContext.peak >= 2, "requests overlap across slots"
     s = summarize(done, warmup_s=0.0, duration_s=reqs[-1].arrival)
     assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_one_tile_requests_are_solved_in_batches_by_the_group_slot():
+    reqs = _trace(150, 2000.0, 11, n_lo=30, n_hi=700)
+    srv = Server(hbm_budget_bytes=1 << 40, large_workers=2, small_workers=2, small_n=512,
+                 context_factory=FakeContext, group_n=256, group_max=16)
+    done = srv.replay(reqs, timeout_s=60)
+    assert len(done) == len(reqs) and not any(r.error for r in done)
+    for r in done:
+        p, o = FakeContext._answer(r.A)
+        np.testing.assert_array_equal(r.perm, p)
+        assert r.objective == o
+        assert (r.worker == "group0") == (2 <= r.n <= 256)
+    group_ctx = [c for name, c, _ in srv.slots if name == "group0"][0]
+    sizes = [k for kind, k, _ in group_ctx.calls if kind == "solve_many"]
+    assert all(kind == "solve_many" for kind, _, _ in group_ctx.calls)
+    assert max(sizes) > 1 and max(sizes) <= 16  # batches, capped at group_max
+    assert sum(sizes) == sum(1 for r in reqs if 2 <= r.n <= 256)
+    s = summarize(done, warmup_s=0.0, duration_s=reqs[-1].arrival)
+    assert s["by_group"] == sum(sizes)
 
 
 def test_a_request_is_admitted_while_another_runs():
@@ -127,12 +153,18 @@ def test_request_larger_than_the_budget_is_refused_not_run():
 
 class FailingContext(FakeContext):
     """Raises for every request whose A[0, 1] is negative (a stand-in for a
-    FramError from the library), solves the others."""
+    FramError from the library), solves the others; a batch with such a
+    request fails as a whole, like fram_solve_many."""
 
     def solve(self, A, B, **kw):
         if A[0, 1] < 0:
             raise RuntimeError("fram_solve_ex: status 4 (numeric)")
         return super().solve(A, B, **kw)
+
+    def solve_many(self, As, Bs, **kw):
+        if any(A[0, 1] < 0 for A in As):
+            raise RuntimeError("fram_solve_many_ex: status 4 (numeric)")
+        return super().solve_many(As, Bs, **kw)
 
 
 def test_a_failing_request_is_reported_and_its_slot_keeps_serving():
@@ -178,6 +210,14 @@ class ResidentContext(FakeContext):
         self._account()
         return super().solve(A, B, **kw)
 
+    def solve_many(self, As, Bs, **kw):
+        from paper_2508_00887_amd.serve import Server as S
+        need = sum(S._bytes(self.server, S._edge(A.shape[0])) for A in As)
+        self.fixed = 8192
+        self.ws = max(self.ws, need)
+        self._account()
+        return super().solve_many(As, Bs, **kw)
+
     def trim(self):
         self.ws = 0
         self._account()
@@ -218,12 +258,17 @@ def test_served_results_equal_solving_alone():
     done = srv.replay(reqs, timeout_s=300)
     assert len(done) == len(reqs) and not any(r.error for r in done)
     assert len({r.worker for r in done}) >= 2
+    assert any(r.worker == "group0" for r in done)
     # the larger requests projected on chip (launches ordered across the
     # slots' streams); the comparison below is with streaming passes alone
     assert any(r.stats["sdsn_onchip"] > 0 for r in done)
     with Context(0) as ctx:
         for r in done:
+            # grouped requests: the single-pair solve with their one-tile edge
+            kw = {}
+            if r.worker == "group0":
+                kw["tile"] = 64 if r.n <= 64 else 128 if r.n <= 128 else 256
             p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stall_iters=3,
-                                sdsn_mode="stream")
+                                sdsn_mode="stream", **kw)
             np.testing.assert_array_equal(r.perm, p)
             assert r.objective == o
