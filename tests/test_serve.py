@@ -264,8 +264,9 @@ def test_served_results_equal_solving_alone():
     assert any(r.stats["sdsn_onchip"] > 0 for r in done)
     with Context(0) as ctx:
         for r in done:
-            # grouped requests: the single-pair solve with their one-tile edge
-            kw = {}
+            # grouped requests: the single-pair solve with their one-tile edge;
+            # slot requests: with the server's slot tile
+            kw = {"tile": srv.slot_tile}
             if r.worker == "group0":
                 kw["tile"] = 64 if r.n <= 64 else 128 if r.n <= 128 else 256
             p, o, _ = ctx.solve(r.A, r.B, iters=100, tol=1e-6, prec="bf16", stall_iters=3,
