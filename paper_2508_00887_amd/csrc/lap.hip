@@ -46,7 +46,11 @@ __host__ __device__ inline LapBidState bid_carve(char* ws, int n) {
 // Smallest n for which the assignment bids in parallel rounds first.
 constexpr int kBidMinN = 1024;
 // Rounds launched (the kernels of the rounds after the stop return at once).
-constexpr int kBidRounds = 64;
+// On the n = 4000 workloads the rounds still match a row every few rounds
+// after 64 of them, each saving a path search far longer than a round
+// (measured assignment: 16.3 ms with 64 rounds, 15.6 ms with 128, 23.8 ms with
+// 256 before the search read ahead, against 23.1 with 128).
+constexpr int kBidRounds = 128;
 
 // Start of the bidding rounds: u = -row maxima (given), v = the column
 // minima, the tight argmax pairs matched (a column to its lowest claiming
@@ -166,21 +170,22 @@ __global__ __launch_bounds__(NT) void lap_kernel(LapProblem one,
   if (threadIdx.x == 0 && p.paths_out != nullptr) *p.paths_out = r;
 }
 
-// One problem with its row reduction given, n <= 256 * C: the solver with
-// the column state in registers (lap_solve_reg), 256 threads.
-template <int C>
-__global__ __launch_bounds__(256) void lap_reg_kernel(LapProblem p, int after_bids) {
+// One problem with its row reduction given, n <= NT * C: the solver with
+// the column state in registers (lap_solve_reg), NT threads.  V4: rows read
+// as whole float4 groups (n % 4 == 0, n >= 4, 16-byte aligned rows).
+template <int NT, int C, bool V4>
+__global__ __launch_bounds__(NT) void lap_reg_kernel(LapProblem p, int after_bids) {
   extern __shared__ __align__(16) char lds[];
-  __shared__ LapShared<4> sh;
+  __shared__ LapShared<NT / 64> sh;
   const LapRegArrays a = lap_reg_carve(lds, p.n);
   const double* vpart = reinterpret_cast<const double*>(p.ws + vpart_offset(p.n));
   const LapBidState bs = bid_carve(p.ws, p.n);
-  const int r = lap_solve_reg<256, C>(p.w, p.n, (size_t)p.ld, p.sigma, p.u_init, vpart,
-                                      col_chunks(p.n), a, sh, after_bids ? &bs : nullptr);
+  const int r = lap_solve_reg<NT, C, V4>(p.w, p.n, (size_t)p.ld, p.sigma, p.u_init, vpart,
+                                         col_chunks(p.n), a, sh, after_bids ? &bs : nullptr);
   if (threadIdx.x == 0 && p.paths_out != nullptr) *p.paths_out = r;
 }
 
-template <int C>
+template <int NT, int C>
 hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
   const int n = p.n;
   const bool bids = n >= kBidMinN;
@@ -200,10 +205,17 @@ hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
     }
   }
   const size_t shm = lap_reg_lds_bytes(n);
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lap_reg_kernel<C>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const bool v4 = n >= 4 && n % 4 == 0 && p.ld % 4 == 0 &&
+                  (reinterpret_cast<uintptr_t>(p.w) & 15) == 0;
+  const void* fn = v4 ? reinterpret_cast<const void*>(&lap_reg_kernel<NT, C, true>)
+                      : reinterpret_cast<const void*>(&lap_reg_kernel<NT, C, false>);
+  const hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  lap_reg_kernel<C><<<1, 256, shm, s>>>(p, bids ? 1 : 0);
+  if (v4)
+    lap_reg_kernel<NT, C, true><<<1, NT, shm, s>>>(p, bids ? 1 : 0);
+  else
+    lap_reg_kernel<NT, C, false><<<1, NT, shm, s>>>(p, bids ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -234,9 +246,9 @@ hipError_t launch_lap(const LapProblem* one, const LapProblem* probs, int count,
   // A single problem with its row reduction given and n <= 4096: the
   // register-resident solver.
   if (one != nullptr && p1.u_ready && p1.n > 0) {
-    if (p1.n <= 256 * 4) return launch_lap_reg<4>(p1, s);
-    if (p1.n <= 256 * 8) return launch_lap_reg<8>(p1, s);
-    if (p1.n <= 256 * 16) return launch_lap_reg<16>(p1, s);
+    if (p1.n <= 256 * 4) return launch_lap_reg<256, 4>(p1, s);
+    if (p1.n <= 256 * 8) return launch_lap_reg<256, 8>(p1, s);
+    if (p1.n <= 256 * 16) return launch_lap_reg<256, 16>(p1, s);
   }
   const bool lds = lap_in_lds(max_n);
   const size_t shm = lds ? lap_array_bytes(max_n) : 0;

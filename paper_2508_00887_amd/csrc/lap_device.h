@@ -68,6 +68,8 @@ template <int NW>
 struct LapShared {
   double wd[2][NW];
   int wj[2][NW];
+  double w2d[2][NW];  // per wave: the best column outside the wave's best thread
+  int w2j[2][NW];
   int cnt[NW];
   double b1[NW], b2[NW];  // per-wave best and second-best reduced cost of a bid
   int c1[NW], c2[NW];     // ... and their columns
@@ -157,6 +159,35 @@ __device__ __forceinline__ void lap_wave_top2(double& m1, int& j1, double& m2, i
   j1 = k1;
   m2 = r2;
   j2 = k2;
+}
+
+// Minimum over the 64 lanes of a wave, in every lane (no NaN may take part:
+// then the minimum of doubles is exact, and unique up to the sign of zero).
+__device__ __forceinline__ double lap_wave_fmin(double d) {
+  d = fmin(d, lap_dpp<0xB1>(d));
+  d = fmin(d, lap_dpp<0x4E>(d));
+  d = fmin(d, lap_dpp<0x141>(d));
+  d = fmin(d, lap_dpp<0x140>(d));
+  return fmin(fmin(lap_readlane(d, 0), lap_readlane(d, 16)),
+              fmin(lap_readlane(d, 32), lap_readlane(d, 48)));
+}
+__device__ __forceinline__ int lap_wave_imin(int k) {
+  k = min(k, lap_dpp<0xB1>(k));
+  k = min(k, lap_dpp<0x4E>(k));
+  k = min(k, lap_dpp<0x141>(k));
+  k = min(k, lap_dpp<0x140>(k));
+  return min(min(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
+             min(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
+}
+
+// Lexicographic minimum of (d, k) over a wave's lanes, in every lane, in two
+// stages: the least d, then the least k among the lanes holding it.  Equal to
+// the pairwise lexicographic reduction for NaN-free d (-0 and +0 compare
+// equal in both).
+__device__ __forceinline__ void lap_wave_lexmin(double& d, int& k) {
+  const double m = lap_wave_fmin(d);
+  k = lap_wave_imin(d == m ? k : INT_MAX);
+  d = m;
 }
 
 // Solves max_sigma sum_i W[i, sigma(i)] for the n x n block of W (leading
@@ -567,7 +598,28 @@ __device__ __forceinline__ void lap_row_cols(const float* __restrict__ row, int 
   }
 }
 
-template <int NT, int C>
+// Row i's entries in this thread's columns, the same for every thread: C / 4
+// float4 reads, those of column groups past n clamped to the row's last four
+// columns (their values are never used: such columns enter every search as
+// scanned, at distance inf).  Needs n % 4 == 0, n >= 4 and 16-byte aligned
+// rows.  With no per-thread branch, a read issued ahead stays in flight until
+// its registers are used.
+template <int C>
+__device__ __forceinline__ void lap_row_cols4(const float* __restrict__ row, int j0, int n,
+                                              float (&x)[C]) {
+#pragma unroll
+  for (int q = 0; q < C / 4; ++q) {
+    const int jj = (j0 + 4 * q < n) ? j0 + 4 * q : n - 4;
+    const float4 t = *reinterpret_cast<const float4*>(row + jj);
+    x[4 * q] = t.x;
+    x[4 * q + 1] = t.y;
+    x[4 * q + 2] = t.z;
+    x[4 * q + 3] = t.w;
+  }
+}
+
+// V4: rows read by lap_row_cols4 (the caller checks its conditions).
+template <int NT, int C, bool V4>
 __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int32_t* sigma,
                              const double* __restrict__ u_init, const double* v_part,
                              int v_chunks, LapRegArrays a, LapShared<NT / 64>& sh,
@@ -580,6 +632,12 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
   const double inf = __builtin_inf();
   const int j0 = tid * C;
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
+  auto load_row = [&](int r, float(&dst)[C]) {
+    if constexpr (V4)
+      lap_row_cols4<C>(W + (size_t)r * ld, j0, n, dst);
+    else
+      lap_row_cols<C>(W + (size_t)r * ld, j0, n, vec, dst);
+  };
 
   double v[C];
   if (given != nullptr) {
@@ -673,7 +731,7 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
         }
         --budget;
         const int i = a.freel[k++];
-        lap_row_cols<C>(W + (size_t)i * ld, j0, n, vec, x);
+        load_row(i, x);
         double m1 = inf, m2 = inf;
         int j1 = INT_MAX, j2 = INT_MAX;
 #pragma unroll
@@ -743,81 +801,146 @@ __device__ int lap_solve_reg(const float* __restrict__ W, int n, size_t ld, int3
   }
 
   // ---- one shortest augmenting path per row still unmatched
+  //
+  // Each step scans the column of least tentative distance and relaxes the
+  // unscanned columns through the row matched to it, whose entries are a
+  // dependent read of W.  Most often (three steps in four on the n = 4000
+  // workloads) the next step's column is the best one outside the thread that
+  // holds this step's column, so that column's row is read ahead, during the
+  // relaxation and the next step's search, and used when the guess was right.
+  // The guess only decides what is read early: the path is the same.
   int fail = 0;
   int par = 0;
+  float xs[C];  // the second row buffer of the path search
   for (int k = 0; k < nfree; ++k) {
     const int i0 = a.freel[k];
     const double ui0 = a.u[i0];
-    lap_row_cols<C>(W + (size_t)i0 * ld, j0, n, vec, x);
+    load_row(i0, x);
     double dist[C];
+    int pr[C];  // predecessor rows, kept here until the path is complete
     unsigned scanned = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = j0 + c;
+      pr[c] = i0;
       if (j < n) {
         dist[c] = (-(double)x[c] - ui0) - v[c];
-        a.pred[j] = i0;
       } else {
         dist[c] = inf;
         scanned |= 1u << c;
       }
     }
+    int ipre = -1;
     int jend = -1;
     double D = 0.0;
-    while (true) {
-      // Order: distance, then unmatched before matched, then column (key
-      // j for an unmatched column, n + j for a matched one).
-      double bd = inf;
-      int bj = INT_MAX;
+    // One step of the search.  cur holds row ipre's entries, read ahead by
+    // the previous step; nxt receives the read ahead for the next one.  The
+    // steps alternate the two buffers, so a read ahead lands in the registers
+    // it is used from (no copy that would wait for it).  Returns 0 to go on,
+    // 1 when the path ends at an unmatched column, 2 when no finite distance
+    // is left.
+    auto step = [&](float(&cur)[C], float(&nxt)[C]) -> int {
+      // This thread's least unscanned column.  Order: distance, then
+      // unmatched before matched, then column (key j for an unmatched column,
+      // n + j for a matched one).  Scanned columns and NaN distances enter as
+      // (inf, INT_MAX), as in a scan that takes a column only when it is
+      // lexicographically below the best so far, starting from (inf,
+      // INT_MAX).  The minimum in two stages: the least distance (a tree),
+      // then the least key among the columns at that distance.
+      double td[C];
+      int tk[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const int key = ((freecols >> c) & 1u) ? j0 + c : n + j0 + c;
-        if (!((scanned >> c) & 1u) && (dist[c] < bd || (dist[c] == bd && key < bj))) {
-          bd = dist[c];
-          bj = key;
-        }
+        const bool open = !((scanned >> c) & 1u) && !__builtin_isnan(dist[c]);
+        td[c] = open ? dist[c] : inf;
+        tk[c] = open ? (((freecols >> c) & 1u) ? j0 + c : n + j0 + c) : INT_MAX;
       }
-      lap_wave_min(bd, bj);
+      double dm[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) dm[c] = td[c];
+#pragma unroll
+      for (int h = 1; h < C; h *= 2)
+#pragma unroll
+        for (int c = 0; c + h < C; c += 2 * h) dm[c] = fmin(dm[c], dm[c + h]);
+      const double tmin = dm[0];
+      int km[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) km[c] = td[c] == tmin ? tk[c] : INT_MAX;
+#pragma unroll
+      for (int h = 1; h < C; h *= 2)
+#pragma unroll
+        for (int c = 0; c + h < C; c += 2 * h) km[c] = min(km[c], km[c + h]);
+      const int kmin = km[0];
+      // The wave's least column, then its least outside the thread holding
+      // that one (the read-ahead guess).
+      double bd = tmin;
+      int bj = kmin;
+      lap_wave_lexmin(bd, bj);
+      const bool mine = kmin == bj;
+      double gd = mine ? inf : tmin;
+      int gj = mine ? INT_MAX : kmin;
+      lap_wave_lexmin(gd, gj);
       if (lane == 0) {
         sh.wd[par][wave] = bd;
         sh.wj[par][wave] = bj;
+        sh.w2d[par][wave] = gd;
+        sh.w2j[par][wave] = gj;
       }
       __syncthreads();
       bd = sh.wd[par][0];
       bj = sh.wj[par][0];
+      gd = sh.w2d[par][0];
+      gj = sh.w2j[par][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) lap_better(bd, bj, sh.wd[par][w], sh.wj[par][w]);
+      for (int w = 1; w < NW; ++w)
+        lap_top2_merge(bd, bj, gd, gj, sh.wd[par][w], sh.wj[par][w], sh.w2d[par][w],
+                       sh.w2j[par][w]);
       par ^= 1;
-      if (bj == INT_MAX) {  // no finite distance left
-        fail = 1;
-        break;
-      }
+      if (bj == INT_MAX) return 2;
       if (bj >= n) bj -= n;
       if (bj >= j0 && bj < j0 + C) scanned |= 1u << (bj - j0);
       const int i = a.row_of[bj];
       if (i == -1) {
         jend = bj;
         D = bd;
-        break;
+        return 1;
       }
-      // Relax the unscanned columns through row i (matched to column bj).
+      // Row i (matched to column bj): already in cur when the last guess
+      // named it, else read now; then read ahead the guess for the next
+      // step, the row matched to column gj (row i again when there is none:
+      // a read that is never used, but every path then issues the same
+      // reads, so waiting for cur never waits for the read ahead).
+      int inext = -1;
+      if (gj != INT_MAX) {
+        const int g = gj >= n ? gj - n : gj;
+        if (g >= 0 && g < n) inext = a.row_of[g];
+      }
       const double ui = a.u[i];
-      lap_row_cols<C>(W + (size_t)i * ld, j0, n, vec, x);
+      if (i != ipre) load_row(i, cur);
+      ipre = (inext >= 0 && inext < n) ? inext : i;
+      load_row(ipre, nxt);
+      // Relax the unscanned columns through row i.
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        if ((scanned >> c) & 1u) continue;
-        const double nd = ((bd + (-(double)x[c])) - ui) - v[c];
-        if (nd < dist[c]) {
-          dist[c] = nd;
-          a.pred[j0 + c] = i;
-        }
+        const double nd = ((bd + (-(double)cur[c])) - ui) - v[c];
+        const bool upd = !((scanned >> c) & 1u) && nd < dist[c];
+        dist[c] = upd ? nd : dist[c];
+        pr[c] = upd ? i : pr[c];
       }
+      return 0;
+    };
+    int r;
+    while (true) {
+      if ((r = step(x, xs)) != 0) break;
+      if ((r = step(xs, x)) != 0) break;
     }
+    if (r == 2) fail = 1;
     if (fail) break;
-    // Potentials, as in lap_solve.
+    // Predecessors to LDS for the flip, and the potentials, as in lap_solve.
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = j0 + c;
+      if (j < n) a.pred[j] = pr[c];
       if (!((scanned >> c) & 1u) || j >= n || j == jend) continue;
       v[c] += dist[c] - D;
       a.u[a.row_of[j]] += D - dist[c];

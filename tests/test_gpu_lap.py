@@ -65,10 +65,11 @@ def test_assign_random_matches_oracle(ctx, n):
     assert value(W, p) == value(W, ref)
 
 
-# n <= 4096 runs the register solver (64 and 777 with sequential bids, 2048 and 4000
-# after parallel bidding rounds); 4500 keeps the arrays of the other solver in LDS,
+# n <= 4096 runs the register solver (64 and 777 with sequential bids, 2048 to 4001
+# after parallel bidding rounds; 777, 3998 and 4001 read rows column by column, the
+# others as whole float4 groups); 4500 keeps the arrays of the other solver in LDS,
 # 6000 and 10000 in the workspace.
-@pytest.mark.parametrize("n", [64, 777, 2048, 4000, 4500, 6000, 10000])
+@pytest.mark.parametrize("n", [64, 777, 2048, 3998, 4000, 4001, 4500, 6000, 10000])
 def test_assign_near_permutation_matches_oracle(ctx, n):
     W = near_permutation(n, seed=n, collide_frac=0.05)
     p = ctx.assign(W)
