@@ -6,8 +6,9 @@
 // contiguous 16-byte run of one row, loaded straight into LDS and read back
 // with 128-bit LDS reads.
 //
-// Tiling for gfx950: a workgroup of 4 waves (2 x 2) owns a BM x BM output
-// tile; each wave owns (BM/2) x (BM/2) as a grid of 32 x 32 MFMA blocks
+// Tiling for gfx950: a workgroup of 4 waves (2 x 2; 8 waves, 2 x 4, at
+// BM = 256) owns a BM x BM output tile; each wave owns (BM/2) x (BM/2) (or
+// 128 x 64) as a grid of 32 x 32 MFMA blocks
 // (v_mfma_f32_32x32x16_{bf16,f16}, or four v_mfma_f32_32x32x2_f32 per 16-byte
 // chunk for the FP32 path).  K advances 128 bytes of each row per step
 // (64 bf16/f16 or 32 f32 elements) through a two-stage LDS ring with a
@@ -78,14 +79,30 @@ constexpr int kChunks = 8;  // 16-byte chunks per LDS row (128 bytes of K)
 // chunk in 8 different places per row parity.
 __device__ __forceinline__ int swz(int row, int ch) { return ch ^ ((row >> 1) & 7); }
 
-// Output tile (tm, tn) of C = P * Q^T: one workgroup of 256 threads.
+// Waves per workgroup: a 2 x (NW / 2) grid of waves over the output tile.
+// At BM = 256 eight waves (128 x 64 each, 128 accumulator registers) put two
+// waves on every SIMD, so one wave's MFMAs run while the other waits for
+// memory; four waves of 128 x 128 would leave each SIMD idle for the whole of
+// every read that misses the L2.
+template <int BM>
+constexpr int gemm_waves() {
+  return BM == 256 ? 8 : 4;
+}
+
+// Output tile (tm, tn) of C = P * Q^T: one workgroup of 64 * gemm_waves<BM>
+// threads.
 template <Elem E, int BM, bool OUT_F32>
 __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* __restrict__ Q,
                                           void* __restrict__ C, const float* __restrict__ bias,
                                           int ld, int ktiles, int tm, int tn) {
-  constexpr int WT = BM / 2;          // wave tile edge
-  constexpr int F = WT / 32;          // MFMA blocks per wave tile edge
-  constexpr int LOADS = BM * kChunks / 256;
+  constexpr int NW = gemm_waves<BM>();
+  constexpr int NT = 64 * NW;
+  constexpr int WTM = BM / 2;          // wave tile rows
+  constexpr int WTN = BM / (NW / 2);   // wave tile columns
+  constexpr int FM = WTM / 32;         // MFMA blocks per wave tile, rows
+  constexpr int FN = WTN / 32;         // ... and columns
+  constexpr int RPL = NT / kChunks;    // rows one load step covers
+  constexpr int LOADS = BM / RPL;
   __shared__ v4u smem[2][2][BM][kChunks];
 
   const int tid = threadIdx.x;
@@ -93,24 +110,24 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
   const int wave = tid >> 6;
   const int m0 = tm * BM;
   const int n0 = tn * BM;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / (NW / 2), wn = wave % (NW / 2);
   const int ldc = ld / Mfma<E>::kPerChunk;  // leading dimension in chunks
 
-  f32x16 acc[F][F];
+  f32x16 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < F; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
-  const int lrow = tid >> 3;  // 0..31
-  const int lch = tid & 7;
+  const int lrow = tid / kChunks;  // 0 .. RPL - 1
+  const int lch = tid % kChunks;
   const int half = lane >> 5;
   const int l32 = lane & 31;
   const v4u* pg = P + (size_t)(m0 + lrow) * ldc + lch;
   const v4u* qg = Q + (size_t)(n0 + lrow) * ldc + lch;
-  const size_t rstep = (size_t)32 * ldc;  // 32 rows further down
+  const size_t rstep = (size_t)RPL * ldc;  // RPL rows further down
 
   // Prefetch registers for the next K tile.  No lambdas here: an array that a
   // lambda captures by reference is kept in scratch memory.
@@ -122,7 +139,7 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
   }
 #pragma unroll
   for (int i = 0; i < LOADS; ++i) {
-    const int r = lrow + 32 * i;
+    const int r = lrow + RPL * i;
     smem[0][0][r][swz(r, lch)] = ra[i];
     smem[0][1][r][swz(r, lch)] = rb[i];
   }
@@ -140,12 +157,15 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
       }
     }
     // Fragments of step s + 1 are read from LDS while step s runs on MFMA.
-    v4u a[2][F], b[2][F];
+    v4u a[2][FM], b[2][FN];
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const int ra_ = wm * WT + f * 32 + l32;
-      const int rb_ = wn * WT + f * 32 + l32;
+    for (int f = 0; f < FM; ++f) {
+      const int ra_ = wm * WTM + f * 32 + l32;
       a[0][f] = smem[st][0][ra_][swz(ra_, half)];
+    }
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const int rb_ = wn * WTN + f * 32 + l32;
       b[0][f] = smem[st][1][rb_][swz(rb_, half)];
     }
 #pragma unroll
@@ -154,10 +174,13 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
       if (s + 1 < kChunks / 2) {
         const int ch = 2 * (s + 1) + half;
 #pragma unroll
-        for (int f = 0; f < F; ++f) {
-          const int ra_ = wm * WT + f * 32 + l32;
-          const int rb_ = wn * WT + f * 32 + l32;
+        for (int f = 0; f < FM; ++f) {
+          const int ra_ = wm * WTM + f * 32 + l32;
           a[cur ^ 1][f] = smem[st][0][ra_][swz(ra_, ch)];
+        }
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          const int rb_ = wn * WTN + f * 32 + l32;
           b[cur ^ 1][f] = smem[st][1][rb_][swz(rb_, ch)];
         }
       }
@@ -166,15 +189,15 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
       // latency); for FP32 its own order measured slightly faster.
       if constexpr (E != Elem::F32) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int i = 0; i < F; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < F; ++j) Mfma<E>::mac(a[cur][i], b[cur][j], acc[i][j]);
+        for (int j = 0; j < FN; ++j) Mfma<E>::mac(a[cur][i], b[cur][j], acc[i][j]);
       if constexpr (E != Elem::F32) __builtin_amdgcn_sched_barrier(0);
     }
     if (more) {
 #pragma unroll
       for (int i = 0; i < LOADS; ++i) {
-        const int r = lrow + 32 * i;
+        const int r = lrow + RPL * i;
         smem[st ^ 1][0][r][swz(r, lch)] = ra[i];
         smem[st ^ 1][1][r][swz(r, lch)] = rb[i];
       }
@@ -185,15 +208,15 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
   // Accumulator layout of a 32x32 MFMA block: element 4*g + r of lane l is
   // row 8*g + 4*(l/32) + r, column l%32.
 #pragma unroll
-  for (int i = 0; i < F; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const size_t row = (size_t)(m0 + wm * WT + i * 32 + 8 * g + 4 * half + r);
-          const size_t col = (size_t)(n0 + wn * WT + j * 32 + l32);
+          const size_t row = (size_t)(m0 + wm * WTM + i * 32 + 8 * g + 4 * half + r);
+          const size_t col = (size_t)(n0 + wn * WTN + j * 32 + l32);
           float v = acc[i][j][4 * g + r];
           if (OUT_F32 && bias != nullptr) v += bias[row * ld + col];
           if (OUT_F32)
@@ -204,11 +227,9 @@ __device__ __forceinline__ void gemm_tile(const v4u* __restrict__ P, const v4u* 
 }
 
 template <Elem E, int BM, bool OUT_F32>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
-                                                      const v4u* __restrict__ Q,
-                                                      void* __restrict__ C,
-                                                      const float* __restrict__ bias, int np,
-                                                      int ld, int ktiles) {
+__global__ __launch_bounds__(64 * gemm_waves<BM>()) void gemm_nt_kernel(
+    const v4u* __restrict__ P, const v4u* __restrict__ Q, void* __restrict__ C,
+    const float* __restrict__ bias, int np, int ld, int ktiles) {
   const int nbn = np / BM;
   const int bid = blockIdx.x;
   const int ntiles = gridDim.x;
@@ -227,7 +248,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const v4u* __restrict__ P,
 // Many independent products (one job each, blockIdx.y), each one tile of
 // edge BM (np == BM): the GEMMs of a group of small pairs in one launch.
 template <Elem E, int BM, bool OUT_F32>
-__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmJob* __restrict__ jobs) {
+__global__ __launch_bounds__(64 * gemm_waves<BM>()) void gemm_group_kernel(
+    const GemmJob* __restrict__ jobs) {
   const GemmJob j = jobs[blockIdx.y];
   gemm_tile<E, BM, OUT_F32>(static_cast<const v4u*>(j.P), static_cast<const v4u*>(j.Q), j.C,
                             nullptr, j.ld, j.ktiles, 0, 0);
@@ -238,13 +260,13 @@ hipError_t launch_group_e(int bm, const GemmJob* jobs, int count, hipStream_t s)
   const dim3 grid(1, count);
   switch (bm) {
     case 64:
-      gemm_group_kernel<E, 64, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      gemm_group_kernel<E, 64, OUT_F32><<<grid, 64 * gemm_waves<64>(), 0, s>>>(jobs);
       break;
     case 128:
-      gemm_group_kernel<E, 128, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      gemm_group_kernel<E, 128, OUT_F32><<<grid, 64 * gemm_waves<128>(), 0, s>>>(jobs);
       break;
     case 256:
-      gemm_group_kernel<E, 256, OUT_F32><<<grid, 256, 0, s>>>(jobs);
+      gemm_group_kernel<E, 256, OUT_F32><<<grid, 64 * gemm_waves<256>(), 0, s>>>(jobs);
       break;
     default:
       return hipErrorInvalidValue;
@@ -258,18 +280,21 @@ hipError_t launch_e(int bm, const void* P, const void* Q, void* C, const float* 
   const int kelems = kChunks * Mfma<E>::kPerChunk;
   const int ktiles = (n + kelems - 1) / kelems;
   const int nb = np / bm;
-  dim3 grid(nb * nb), block(256);
+  dim3 grid(nb * nb);
   const v4u* p = static_cast<const v4u*>(P);
   const v4u* q = static_cast<const v4u*>(Q);
   switch (bm) {
     case 64:
-      gemm_nt_kernel<E, 64, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
+      gemm_nt_kernel<E, 64, OUT_F32><<<grid, 64 * gemm_waves<64>(), 0, s>>>(p, q, C, bias, np, ld,
+                                                                           ktiles);
       break;
     case 128:
-      gemm_nt_kernel<E, 128, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
+      gemm_nt_kernel<E, 128, OUT_F32><<<grid, 64 * gemm_waves<128>(), 0, s>>>(p, q, C, bias, np,
+                                                                             ld, ktiles);
       break;
     case 256:
-      gemm_nt_kernel<E, 256, OUT_F32><<<grid, block, 0, s>>>(p, q, C, bias, np, ld, ktiles);
+      gemm_nt_kernel<E, 256, OUT_F32><<<grid, 64 * gemm_waves<256>(), 0, s>>>(p, q, C, bias, np,
+                                                                             ld, ktiles);
       break;
     default:
       return hipErrorInvalidValue;
