@@ -101,14 +101,16 @@ __global__ __launch_bounds__(256) void bid_list_kernel(LapBidState s, int n,
   if (s.row_of[t] == INT_MAX) s.row_of[t] = -1;
 }
 
-// Round r (list p = r & 1): one wave per listed row.
+// Round r (list p = r & 1): one wave per listed row, the grid's waves
+// striding over the list (a grid sized for the first round's list would
+// mostly start empty blocks in the later, short rounds).
 __global__ __launch_bounds__(256) void bid_round_kernel(LapBidState s, const float* __restrict__ W,
                                                         int n, int ld, int p) {
   if (s.ctl[2] != 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) s.ctl[p ^ 1] = 0;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= s.ctl[p]) return;
-  lap_bid_row(W, n, (size_t)ld, s, s.list[p][w]);
+  const int count = s.ctl[p];
+  for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < count; w += gridDim.x * 4)
+    lap_bid_row(W, n, (size_t)ld, s, s.list[p][w]);
 }
 
 __global__ __launch_bounds__(256) void bid_resolve_kernel(LapBidState s, int p) {
@@ -194,12 +196,13 @@ hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
     const LapBidState bs = bid_carve(p.ws, n);
     const double* vpart = reinterpret_cast<const double*>(p.ws + vpart_offset(n));
     const int blocks = (n + 255) / 256;
+    const int round_blocks = (n + 3) / 4 < 256 ? (n + 3) / 4 : 256;
     bid_init_kernel<<<blocks, 256, 0, s>>>(bs, n, p.u_init, vpart, col_chunks(n));
     bid_match_kernel<<<blocks, 256, 0, s>>>(bs, p.w, n, p.ld, p.sigma);
     bid_list_kernel<<<blocks, 256, 0, s>>>(bs, n, p.sigma);
     for (int r = 0; r < kBidRounds; ++r) {
       const int q = r & 1;
-      bid_round_kernel<<<(n + 3) / 4, 256, 0, s>>>(bs, p.w, n, p.ld, q);
+      bid_round_kernel<<<round_blocks, 256, 0, s>>>(bs, p.w, n, p.ld, q);
       bid_resolve_kernel<<<blocks, 256, 0, s>>>(bs, q);
       bid_control_kernel<<<1, 64, 0, s>>>(bs, q ^ 1);
     }

@@ -496,28 +496,47 @@ __device__ inline void lap_bid_row(const float* __restrict__ W, int n, size_t ld
   const int lane = threadIdx.x & 63;
   const double inf = __builtin_inf();
   const float* ri = W + (size_t)i * ld;
-  double m1 = inf, m2 = inf;
-  int j1 = INT_MAX, j2 = INT_MAX;
-  for (int j = lane; j < n; j += 64) {
-    const double h = -(double)ri[j] - s.v[j];
-    const bool b1 = lap_lex_less(h, j, m1, j1), b2 = lap_lex_less(h, j, m2, j2);
-    m2 = b1 ? m1 : (b2 ? h : m2);
-    j2 = b1 ? j1 : (b2 ? j : j2);
-    m1 = b1 ? h : m1;
-    j1 = b1 ? j : j1;
+  // Best two (value, column) pairs of this lane's columns: four independent
+  // chains (columns j, j + 64, j + 128, j + 192 of each 256-column block) so
+  // that four reads and comparisons are in flight, merged at the end (the
+  // columns are distinct, so the best two do not depend on the order).
+  double m1[4], m2[4];
+  int j1[4], j2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    m1[t] = m2[t] = inf;
+    j1[t] = j2[t] = INT_MAX;
   }
-  lap_wave_top2(m1, j1, m2, j2);
+  auto take = [&](int t, int j) {
+    const double h = -(double)ri[j] - s.v[j];
+    const bool b1 = lap_lex_less(h, j, m1[t], j1[t]), b2 = lap_lex_less(h, j, m2[t], j2[t]);
+    m2[t] = b1 ? m1[t] : (b2 ? h : m2[t]);
+    j2[t] = b1 ? j1[t] : (b2 ? j : j2[t]);
+    m1[t] = b1 ? h : m1[t];
+    j1[t] = b1 ? j : j1[t];
+  };
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) take(t, j + 64 * t);
+  }
+  for (; j < n; j += 64) take(0, j);
+#pragma unroll
+  for (int t = 1; t < 4; ++t) lap_top2_merge(m1[0], j1[0], m2[0], j2[0], m1[t], j1[t], m2[t], j2[t]);
+  double b1 = m1[0], b2 = m2[0];
+  int c1 = j1[0], c2 = j2[0];
+  lap_wave_top2(b1, c1, b2, c2);
   if (lane == 0) {
-    if (j2 == INT_MAX) {  // fewer than two finite choices: left to the paths
+    if (c2 == INT_MAX) {  // fewer than two finite choices: left to the paths
       s.tgt[i] = -1;
       return;
     }
-    const bool lower = m1 < m2;
-    int target = j1;
-    if (!lower && s.row_of[j1] >= 0) target = j2;
-    const double d = lower ? m2 - m1 : 0.0;
+    const bool lower = b1 < b2;
+    int target = c1;
+    if (!lower && s.row_of[c1] >= 0) target = c2;
+    const double d = lower ? b2 - b1 : 0.0;
     s.tgt[i] = target;
-    s.newu[i] = m2;
+    s.newu[i] = b2;
     s.drop[i] = d;
     atomicMax(&s.key[target], lap_bid_key(d, i));
   }
