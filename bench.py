@@ -264,7 +264,8 @@ def main():
     ap.add_argument("--sdsn-mode", default="auto", choices=["auto", "stream", "onchip"])
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-pair leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="timed seconds of the served leg after its 5 s warm-up (the served workload: 30)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32")
     ap.add_argument("--serve-rate", type=float, default=200.0,
