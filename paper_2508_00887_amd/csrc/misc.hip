@@ -257,19 +257,48 @@ __global__ __launch_bounds__(kT) void delta_group_kernel(const UpdateJob* __rest
 }
 
 // ------------------------------------------------------------------ validation
+// Input checks of a graph matrix (finite, non-negative, symmetric) by tile
+// pairs: workgroup (J, I) with I <= J reads tile (I, J) into LDS and tile
+// (J, I) row by row, so both reads are coalesced and each element is
+// compared with its mirror image through LDS.  Every element is checked for
+// finiteness and sign once, every pair (i, j) for symmetry once (a NaN fails
+// both, as NaN != NaN).  Workgroups below the diagonal leave at once.
+constexpr int kVT = 32;  // tile edge (kT = 256 threads: 32 x 8, four rows each)
 __global__ __launch_bounds__(kT) void validate_kernel(const double* __restrict__ A, int n,
                                                       DevState* st) {
+  __shared__ double t[kVT][kVT + 1];
   __shared__ int sflag;
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
   if (threadIdx.x == 0) sflag = 0;
-  __syncthreads();
+  const int tx = threadIdx.x % kVT, ty = threadIdx.x / kVT;
   int f = 0;
-  const size_t total = (size_t)n * n;
-  for (size_t t = (size_t)blockIdx.x * kT + threadIdx.x; t < total; t += (size_t)gridDim.x * kT) {
-    const size_t i = t / n, j = t % n;
-    const double v = A[t];
-    if (!isfinite(v)) f |= 1;
-    if (v < 0.0) f |= 2;
-    if (A[j * n + i] != v) f |= 4;
+#pragma unroll
+  for (int k = 0; k < kVT / 8; ++k) {
+    const int r = bi * kVT + ty + 8 * k, c = bj * kVT + tx;
+    double v = 0.0;
+    if (r < n && c < n) {
+      v = A[(size_t)r * n + c];
+      if (!isfinite(v)) f |= 1;
+      if (v < 0.0) f |= 2;
+    }
+    t[ty + 8 * k][tx] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kVT / 8; ++k) {
+    // Element (r, c) of tile (J, I) mirrors (c, r) of tile (I, J).
+    const int r = bj * kVT + ty + 8 * k, c = bi * kVT + tx;
+    if (r >= n || c >= n) continue;
+    const double m = t[tx][ty + 8 * k];
+    if (bi != bj) {
+      const double v = A[(size_t)r * n + c];
+      if (!isfinite(v)) f |= 1;
+      if (v < 0.0) f |= 2;
+      if (v != m) f |= 4;
+    } else if (t[ty + 8 * k][tx] != m) {
+      f |= 4;
+    }
   }
   if (f) atomicOr(&sflag, f);
   __syncthreads();
@@ -519,7 +548,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_validate(const double* A, int n, DevState* st, hipStream_t s) {
-  validate_kernel<<<grid_for((size_t)n * n), kT, 0, s>>>(A, n, st);
+  if (n < 1) return hipSuccess;
+  const int nt = (n + kVT - 1) / kVT;
+  validate_kernel<<<dim3(nt, nt), kT, 0, s>>>(A, n, st);
   return hipGetLastError();
 }
 

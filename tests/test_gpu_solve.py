@@ -180,6 +180,41 @@ def test_device_entry_point_rejects_invalid_device_input(ctx):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n", [33, 100, 257])
+@pytest.mark.parametrize("defect", ["none", "asym_corner", "asym_tile_edge", "nan_diag",
+                                    "inf_pair", "neg_pair_tail"])
+def test_device_validation_over_tile_pairs(ctx, n, defect):
+    # The device check compares 32 x 32 tiles with their mirror tiles: every
+    # kind of defect, in the first, a straddling and the last (ragged) tile.
+    import torch
+    from paper_2508_00887_amd import FramError
+    import paper_2508_00887_amd.fram as F
+    rng = np.random.default_rng(n)
+    A = np.triu(rng.random((n, n)), 1)
+    A = A + A.T
+    B = A.copy()
+    if defect == "asym_corner":
+        B[0, n - 1] += 1e-9
+    elif defect == "asym_tile_edge":
+        A[32, 31] += 1e-9
+    elif defect == "nan_diag":
+        B[n - 1, n - 1] = np.nan
+    elif defect == "inf_pair":
+        A[n - 1, 0] = A[0, n - 1] = np.inf
+    elif defect == "neg_pair_tail":
+        B[n - 2, n - 1] = B[n - 1, n - 2] = -0.5
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    if defect == "none":
+        perm, _, _ = ctx.solve_dev(dA.data_ptr(), dB.data_ptr(), n, iters=2, tol=0.0)
+        assert sorted(perm.tolist()) == list(range(n))
+    else:
+        with pytest.raises(FramError) as e:
+            ctx.solve_dev(dA.data_ptr(), dB.data_ptr(), n, iters=2, tol=0.0)
+        assert e.value.status == F.FRAM_EINVAL
+    torch.cuda.synchronize()
+
+
 def _small_batch(count, seed, n_hi=160):
     rng = np.random.default_rng(seed)
     return [synth.make_pair(int(rng.integers(20, n_hi + 1)), float(rng.uniform(0.1, 0.5)), 0.03,
