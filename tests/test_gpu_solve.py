@@ -51,6 +51,20 @@ def test_small_workload_fp32_equals_oracle(ctx, seed):
     assert st["outer_iters"] == 100
 
 
+@pytest.mark.parametrize("n", [50, 300])
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_fp32_solve_equals_oracle_for_every_tile_edge(ctx, n, tile):
+    # Every tile edge on small grids: n = 300 at edge 256 is a 2 x 2 grid with
+    # a ragged tail, without the XCD block mapping of the tile grid (the
+    # eight-wave GEMM tile there is otherwise only reached at n = 4000).
+    pr = synth.make_pair(n, 0.3, 0.03, 9500 + n, weights="half_open_top")
+    s_or, obj_or, _, _ = O.solve(pr.A, pr.B, theta=2.0, iters=40)
+    perm, obj, st = ctx.solve(pr.A, pr.B, theta=2.0, iters=40, tol=0.0, prec="fp32", tile=tile)
+    assert st["gemm_tile"] == tile
+    np.testing.assert_array_equal(perm, s_or)
+    assert abs(obj - obj_or) <= 1e-9 * abs(obj_or)
+
+
 @pytest.mark.parametrize("n", [2, 3, 5, 17, 63, 64, 65, 129, 200])
 def test_edge_sizes_fp32_equals_oracle(ctx, n):
     pr = synth.make_pair(n, 0.5, 0.03, 9000 + n, weights="half_open_top")
