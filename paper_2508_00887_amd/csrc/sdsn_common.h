@@ -203,6 +203,15 @@ __device__ __forceinline__ double combine4(double c0, double c1, double c2, doub
 // Global access at a uniform base plus a 32-bit element offset.  Written this
 // way the address is an SGPR base plus a VGPR offset, so loop-invariant 64-bit
 // per-lane addresses are never formed (and never spilled).
+// A wave-uniform double held in scalar registers (its two halves read from
+// the first lane).
+__device__ __forceinline__ double uniform_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <typename T>
 __device__ __forceinline__ T& at_u32(T* base, unsigned off) {
   return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (size_t)(off * (unsigned)sizeof(T)));
@@ -299,9 +308,9 @@ template <int BM, typename Store = PlainStore>
 __device__ __forceinline__ void tile_partials(const float4& cacc, const double* s_rowsum,
                                               float (*s_colred)[BM], double* s_red,
                                               double* rowp, double* colp, double* tot, int bm,
-                                              int bn, int nb, int np, Store st = Store()) {
+                                              int bn, int nb, int np, Store st = Store(),
+                                              int tid = (int)threadIdx.x) {
   using TS = TileShape<BM>;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int q = lane / TS::LPR;
@@ -323,7 +332,7 @@ __device__ __forceinline__ void tile_partials(const float4& cacc, const double* 
     if (p == 0) st(&at_u32(colp, (unsigned)(bm * np + bn * BM + c)), v);
   }
   const double tt = block_sum<TS::NT>(rowsum, s_red);
-  if (tid == 0) st(&tot[bm * nb + bn], tt);
+  if (tid == 0) st(&at_u32(tot, (unsigned)(bm * nb + bn)), tt);
 }
 
 }  // namespace

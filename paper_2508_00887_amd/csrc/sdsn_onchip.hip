@@ -51,7 +51,7 @@
 #include "sdsn_common.h"
 
 #ifndef SDSN_ONCHIP_REG_STEPS
-#define SDSN_ONCHIP_REG_STEPS 10
+#define SDSN_ONCHIP_REG_STEPS 14
 #endif
 
 namespace fram {
@@ -146,10 +146,10 @@ __device__ bool grid_barrier(unsigned* sy, unsigned epoch, long long limit, int*
 }
 
 // Tile steps (float4 per lane) kept in VGPRs; the rest of the tile lives in
-// LDS.  At BM = 256 the whole tile takes 64 of a lane's 128 VGPRs and the
-// pass spills; with 10 of the 16 steps in registers and 6 in LDS (96 KB per
-// workgroup) a pass at n = 4000 takes 13.1 us instead of 15.4 (12 steps:
-// 13.7 us), measured on MI355X.
+// LDS.  At BM = 256 the whole tile takes 64 of a lane's 128 VGPRs; with 14 of
+// the 16 steps in registers and 2 in LDS (32 KB per workgroup) a pass at
+// n = 4000 takes 7.97 us (10 steps: 8.13 us, 12: 8.00, all 16: 8.02), measured
+// on MI355X with nothing spilled.
 template <int BM>
 struct TileSplit {
   static constexpr int IN_REGS = BM == 256 ? SDSN_ONCHIP_REG_STEPS : TileShape<BM>::STEPS;
@@ -257,11 +257,23 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
   double gamma = 0.0;
   bool ok = true;
   const double dn = (double)n;
+  // Launch constants of the P1 correction, held in scalar registers.
+  const double half0 = uniform_f64(0.5 / dn), dn2 = uniform_f64(dn * dn);
   for (;; ++k, ++epoch) {
     ok = grid_barrier(a.sync, epoch, a.wait_ticks, &s_ok);
     if (!ok) break;
     const Partials in = a.p[(k - 1) & 1];
     const Partials out = a.p[k & 1];
+    // The thread index as seen by this pass.  At BM = 256 an opaque copy, so
+    // that the LDS addresses formed from it are formed again in every pass
+    // rather than held in registers across it: at four waves per SIMD a lane
+    // has 128 registers, and addresses held across the pass were spilled to
+    // scratch and reloaded, each reload a full memory wait, every pass
+    // (measured at n = 4000: 8.32 -> 8.13 us per pass, and with the registers
+    // freed 14 tile steps instead of 10 fit in them: 7.97 us).  The smaller
+    // tiles do not spill and run slightly faster without the copy.
+    int tk = tid;
+    if constexpr (BM == 256) asm volatile("" : "+v"(tk));
     // All reads of the previous pass's partials are issued before they are
     // combined: the tile totals, then thread (p, r)'s chains p of row r's and
     // column r's partial sums (combined in a fixed order below).  Addresses
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
     double part = 0.0;
     float m = -INFINITY;
     {
-      const int r = tid % BM, p = tid / BM;
+      const int r = tk % BM, p = tk / BM;
       const double* rb = in.rowp + bm * BM;
       const double* cb = in.colp + bn * BM;
       auto ldr = [&](int b) { return ld_coherent(&at_u32(rb, (unsigned)(b * np + r))); };
@@ -280,8 +292,8 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
       if (nb <= 16) {
         // nb * nb <= NT: one total (and, on the first pass, one tile maximum)
         // per thread, read together with both chains.
-        const bool has_t = tid < nb * nb;
-        const unsigned tt = has_t ? (unsigned)tid : 0u;
+        const bool has_t = tk < nb * nb;
+        const unsigned tt = has_t ? (unsigned)tk : 0u;
         const double tv = ld_coherent(&at_u32(in.tot, tt));
         const float mv = (k == 1) ? ld_coherent(&at_u32(in.tmax, tt)) : -INFINITY;
         chain_sum_pair16(ldr, ldc, nb, p, rsum, csum);
@@ -309,19 +321,20 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
       s = (m > 0.0f) ? (float)(a.theta / (2.0 * (double)m)) : 0.0f;
     }
     const double sd = (double)s;
-    const double half = 0.5 / dn + 0.5 * sd * S / (dn * dn);
-    if (tid < BM) {
-      const double ri = combine4(s_chain[0][0][tid], s_chain[0][1][tid], s_chain[0][2][tid],
-                                 s_chain[0][3][tid]);
-      const double cj = combine4(s_chain[1][0][tid], s_chain[1][1][tid], s_chain[1][2][tid],
-                                 s_chain[1][3][tid]);
+    const double half = half0 + 0.5 * sd * S / dn2;
+    if (tk < BM) {
+      const double ri = combine4(s_chain[0][0][tk], s_chain[0][1][tk], s_chain[0][2][tk],
+                                 s_chain[0][3][tk]);
+      const double cj = combine4(s_chain[1][0][tk], s_chain[1][1][tk], s_chain[1][2][tk],
+                                 s_chain[1][3][tk]);
       // Rows and columns past n get -inf, so their entries (zero) map to
       // max(0, -inf) = 0 without a test per entry.
-      s_a[tid] = (bm * BM + tid < n) ? (float)(half - sd * ri / dn) : -INFINITY;
-      s_b[tid] = (bn * BM + tid < n) ? (float)(half - sd * cj / dn) : -INFINITY;
+      s_a[tk] = (bm * BM + tk < n) ? (float)(half - sd * ri / dn) : -INFINITY;
+      s_b[tk] = (bn * BM + tk < n) ? (float)(half - sd * cj / dn) : -INFINITY;
     }
     __syncthreads();
-    const float4 bt = make_float4(s_b[cl], s_b[cl + 1], s_b[cl + 2], s_b[cl + 3]);
+    const int clk = ((tk & 63) % LPR) * 4;
+    const float4 bt = make_float4(s_b[clk], s_b[clk + 1], s_b[clk + 2], s_b[clk + 3]);
     cacc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int stp = 0; stp < STEPS; ++stp) {
@@ -338,7 +351,7 @@ __global__ __launch_bounds__(4 * BM) void sdsn_onchip_kernel(OnchipArgs a) {
     }
     rows.finish(w, s_rowsum);
     tile_partials<BM>(cacc, s_rowsum, s_colred, s_red, out.rowp, out.colp, out.tot, bm, bn, nb,
-                      np, CoherentStore());
+                      np, CoherentStore(), tk);
   }
   if (!ok) {
     if (tid == 0) atomicOr(&a.st->invalid, kInvalidBarrier);
