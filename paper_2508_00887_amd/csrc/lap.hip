@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void bid_init_kernel(LapBidState s, int n,
                                                        int chunks) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t == 0) {
-    s.ctl[0] = s.ctl[1] = s.ctl[2] = s.ctl[4] = s.ctl[6] = 0;
+    s.ctl[0] = s.ctl[1] = s.ctl[2] = s.ctl[4] = s.ctl[6] = s.ctl[7] = 0;
     s.ctl[3] = n + 1;
   }
   if (t >= n) return;
@@ -103,35 +103,48 @@ __global__ __launch_bounds__(256) void bid_list_kernel(LapBidState s, int n,
 
 // Round r (list p = r & 1): one wave per listed row, the grid's waves
 // striding over the list (a grid sized for the first round's list would
-// mostly start empty blocks in the later, short rounds).
+// mostly start empty blocks in the later, short rounds).  The last workgroup
+// to finish its bids then resolves them -- each column to its largest bid,
+// displaced owners listed for the next round -- and applies the stop rule:
+// no row left, or the count not fallen for kBidStall rounds.  One launch per
+// round.  The bids are written and read at the device-coherent level (agent
+// scope), and every wave waits for its own writes to complete before its
+// workgroup counts itself done in ctl[7], so the last workgroup to count sees
+// every bid without a cache flush (a fence per workgroup and round, which
+// writes the L2 back, cost more than the launches it saves).
 __global__ __launch_bounds__(256) void bid_round_kernel(LapBidState s, const float* __restrict__ W,
                                                         int n, int ld, int p) {
+  __shared__ int s_last;
   if (s.ctl[2] != 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.ctl[p ^ 1] = 0;
+  const int q = p ^ 1;
+  // The next list's count restarts from 0 (agent scope: the last workgroup's
+  // appends, possibly on another XCD, count on from it).
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&s.ctl[q], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int count = s.ctl[p];
   for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < count; w += gridDim.x * 4)
     lap_bid_row(W, n, (size_t)ld, s, s.list[p][w]);
-}
-
-__global__ __launch_bounds__(256) void bid_resolve_kernel(LapBidState s, int p) {
-  if (s.ctl[2] != 0) return;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= s.ctl[p]) return;
-  lap_resolve_row(s, s.list[p][t], p ^ 1);
-}
-
-// After round r: stop once no row is left or the count has not fallen for
-// kBidStall rounds.
-__global__ void bid_control_kernel(LapBidState s, int q) {
-  if (threadIdx.x != 0 || s.ctl[2] != 0) return;
-  const int c = s.ctl[q];
-  if (c < s.ctl[3]) {
-    s.ctl[3] = c;
-    s.ctl[4] = 0;
-  } else {
-    s.ctl[4] += 1;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(&s.ctl[7], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+             (int)gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  for (int t = threadIdx.x; t < count; t += 256) lap_resolve_row(s, s.list[p][t], q);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int c = __hip_atomic_load(&s.ctl[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c < s.ctl[3]) {
+      s.ctl[3] = c;
+      s.ctl[4] = 0;
+    } else {
+      s.ctl[4] += 1;
+    }
+    if (c == 0 || s.ctl[4] >= kBidStall) s.ctl[2] = 1;
+    s.ctl[7] = 0;
   }
-  if (c == 0 || s.ctl[4] >= kBidStall) s.ctl[2] = 1;
 }
 
 // Partial column minima of the reduced costs after the row reduction:
@@ -203,8 +216,6 @@ hipError_t launch_lap_reg(const LapProblem& p, hipStream_t s) {
     for (int r = 0; r < kBidRounds; ++r) {
       const int q = r & 1;
       bid_round_kernel<<<round_blocks, 256, 0, s>>>(bs, p.w, n, p.ld, q);
-      bid_resolve_kernel<<<blocks, 256, 0, s>>>(bs, q);
-      bid_control_kernel<<<1, 64, 0, s>>>(bs, q ^ 1);
     }
   }
   const size_t shm = lap_reg_lds_bytes(n);

@@ -476,7 +476,8 @@ struct LapBidState {
   double* newu;             // per row: its u if it wins (m2)
   double* drop;             // per row: its column's price drop if it wins
   int* ctl;                 // [0..1] list counts, [2] stop, [3] best count, [4] stalled
-                            // rounds, [6] rows the row maxima left free
+                            // rounds, [6] rows the row maxima left free, [7] workgroups
+                            // done with the current round
 };
 
 // Rounds without a smaller unmatched count after which bidding stops.
@@ -528,31 +529,37 @@ __device__ inline void lap_bid_row(const float* __restrict__ W, int n, size_t ld
   lap_wave_top2(b1, c1, b2, c2);
   if (lane == 0) {
     if (c2 == INT_MAX) {  // fewer than two finite choices: left to the paths
-      s.tgt[i] = -1;
+      __hip_atomic_store(&s.tgt[i], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
     const bool lower = b1 < b2;
     int target = c1;
     if (!lower && s.row_of[c1] >= 0) target = c2;
     const double d = lower ? b2 - b1 : 0.0;
-    s.tgt[i] = target;
-    s.newu[i] = b2;
-    s.drop[i] = d;
+    // Read back by the workgroup that resolves the round: written through
+    // to the device-coherent level (agent scope), as is the key.
+    __hip_atomic_store(&s.tgt[i], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&s.newu[i], b2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&s.drop[i], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     atomicMax(&s.key[target], lap_bid_key(d, i));
   }
 }
 
 // After the bids of a round: row i of list p takes its column if its bid won
 // (and resets the column's key for the next round), else stays unmatched.
+// The bids of the round were made by other workgroups: read at the
+// device-coherent level (agent scope).
 __device__ inline void lap_resolve_row(const LapBidState& s, int i, int q) {
-  const int j = s.tgt[i];
+  const int j = __hip_atomic_load(&s.tgt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int again = i;
-  if (j >= 0 && s.key[j] == lap_bid_key(s.drop[i], i)) {
+  const double di = __hip_atomic_load(&s.drop[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (j >= 0 && __hip_atomic_load(&s.key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    lap_bid_key(di, i)) {
     const int i0 = s.row_of[j];
-    s.v[j] -= s.drop[i];
+    s.v[j] -= di;
     s.row_of[j] = i;
     s.col_of[i] = j;
-    s.u[i] = s.newu[i];
+    s.u[i] = __hip_atomic_load(&s.newu[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s.key[j] = 0;
     again = i0;
     if (i0 >= 0) s.col_of[i0] = -1;
